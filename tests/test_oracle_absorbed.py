@@ -1,0 +1,98 @@
+"""Pins for the oracle's v-absorbed walks: start distributions (uniform over
+all of V for the closeness estimator, stationary for Kemeny), visit-count
+expectations (Lemmas 1 and 5), walk-length expectations, loop-included paths
+having the absorbed-walk distribution (Lemma 4), and exact small cases."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import csr, dense, native
+from tests.oracle_fixtures import er256, graph
+
+
+def test_star_walks_are_one_step():
+    g = graph("star", 7)
+    r = native.absorbed(g, 0, 2000, 4, 1, want_start=True)
+    st = r["start"]
+    assert set(np.unique(st)) <= set(range(7))
+    assert (r["len"] == (st != 0)).all()              # a leaf needs one move, the root none
+    assert (r["Y2"][0][0] == 0) and r["Y2"][0][1:].sum() == (st != 0).sum()
+
+
+def test_uniform_start_distribution():
+    g = graph("cycle", 10)
+    r = native.absorbed(g, 3, 50_000, 9, 1, want_start=True, want_y2=False)
+    cnt = np.bincount(r["start"], minlength=10)
+    exp = 5000.0
+    chi2 = ((cnt - exp) ** 2 / exp).sum()
+    assert chi2 < 9 + 6 * math.sqrt(18)
+    assert cnt[3] > 0                                  # the root itself is a possible start
+
+
+def test_stationary_start_distribution():
+    g = graph("barabasi_albert", 30, 2, 5)
+    r = native.absorbed(g, 0, 60_000, 9, 2, want_start=True, want_y2=False)
+    cnt = np.bincount(r["start"], minlength=g.n)
+    exp = 60_000 * g.deg / g.nnz
+    chi2 = ((cnt - exp) ** 2 / exp).sum()
+    assert chi2 < (g.n - 1) + 6 * math.sqrt(2 * (g.n - 1))
+
+
+def test_visit_and_length_expectations_er256():
+    g = er256()
+    v = csr.landmark(g)
+    e = dense.expected_counts(g, v)
+    W = 8192
+    for tag, key in ((1, "len_uniform"), (2, "len_stationary")):
+        r = native.absorbed(g, v, W, 1, tag)
+        ln = r["len"].astype(float)
+        z = (ln.mean() - e[key]) / (ln.std(ddof=1) / math.sqrt(W))
+        assert abs(z) < 4.0
+        assert r["Y2"].sum() == r["len"].sum()        # every move departs from a node != v
+    r = native.absorbed(g, v, W, 2, 1, B=32)
+    est = r["Y2"].astype(float)                       # [B, n] block counts
+    mean = est.sum(0) / W
+    se = est.std(0, ddof=1) * math.sqrt(32) / W      # batch means
+    mask = np.arange(g.n) != v
+    zz = (mean[mask] - e["visits_uniform"][mask]) / se[mask]
+    assert np.abs(zz).max() < 5.0
+    assert (np.abs(zz) < 3).mean() > 0.97
+
+
+def test_trace_is_a_walk_to_root():
+    g = graph("grid", 4, 4)
+    r = native.absorbed(g, 5, 40, 3, 1, trace_walk=17, trace_cap=10_000)
+    tr = r["trace"]
+    assert tr[-1] == 5 and (tr[:-1] != 5).all()
+    assert len(tr) - 1 == r["len"][17]
+    for a, b in zip(tr[:-1], tr[1:]):
+        assert b in g.col[g.rp[a]:g.rp[a + 1]]
+
+
+def test_loop_included_path_has_absorbed_walk_law():
+    # Lemma 4: P[s] read from the stacks of a Wilson sample is distributed as a
+    # v-absorbed walk from s; compare mean lengths with h(s, v)
+    g = graph("grid", 3, 3)
+    v, s = 0, 8
+    L = dense.laplacian(g)
+    h = dense.walk_green(L, v)[s].sum()
+    lens = [len(native.loop_included_path(g.n, v, s, g=g, sample=i, seed=21)) - 1 for i in range(6000)]
+    lens = np.asarray(lens, float)
+    z = (lens.mean() - h) / (lens.std(ddof=1) / math.sqrt(len(lens)))
+    assert abs(z) < 4.0
+
+
+def test_loop_included_path_only_uses_drawn_entries():
+    # every departure of P[s] from u reads an entry of S[u] that the Wilson
+    # sample also drew, so counts along the path never exceed draws[u]
+    g = er256()
+    v = csr.landmark(g)
+    r = native.wilson(g, v, 3, 8, keep=[0, 1, 2], want_y1=False)
+    for q in range(3):
+        for s in (0, 100, 200):
+            if s == v:
+                continue
+            p = native.loop_included_path(g.n, v, s, g=g, sample=q, seed=8)
+            uses = np.bincount(p[:-1], minlength=g.n)
+            assert (uses <= r["draws"][q]).all()
