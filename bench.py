@@ -1,0 +1,142 @@
+"""Benchmark of the hot path: one step = Wilson loop-erased-walk sampling
+(omega trees rooted at the max-degree node), omega uniform-start and omega
+stationary-start absorbed walks, and the FP64 assembly of diag(L^dagger),
+closeness and Kemeny's constant, on a Barabasi-Albert graph n = 100,000,
+m = 5 with omega = 4096 (synthetic input, resident in HBM before timing).
+
+Prints one JSON line.  `value` is walk steps per second (Wilson draws plus
+absorbed-walk draws) of the whole job.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WILSON_BYTES_PER_STEP = 33.0     # offsets 16 + column 4 + draw count 8 + next 4 + tree flag 1
+RETRACE_BYTES_PER_NODE = 5.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(og, root, omega_full, seed, budget_s=15.0):
+    """The oracle (C, OpenMP over samples) on a bounded sample of the same workload."""
+    from oracle import native
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t = time.perf_counter()
+    w = native.wilson(og, root, omega_full, seed, n_samples=64, want_y1=True, threads=threads)
+    dt = time.perf_counter() - t
+    n_s = int(min(omega_full, max(64, 64 * budget_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    w = native.wilson(og, root, omega_full, seed, n_samples=n_s, threads=threads)
+    a1 = native.absorbed(og, root, n_s, seed, 1, omega_total=omega_full, threads=threads)
+    a2 = native.absorbed(og, root, n_s, seed, 2, omega_total=omega_full, want_y2=False, threads=threads)
+    dt = time.perf_counter() - t
+    steps = int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
+    return {"value": steps / dt, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_s} of {omega_full} samples (Wilson + both absorbed-walk kinds), {dt:.1f} s",
+            "trees_per_s": n_s / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--omega", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2311_10290_amd as lap
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, m, omega, seed = 100_000, 5, args.omega, 1
+    log("generating BA(100000, 5)")
+    src, dst = gg.barabasi_albert(n, m, 0)
+    g = lap.Graph(n, src, dst)
+    root = g.max_deg_node
+    out = {k: torch.empty(g.n, dtype=torch.float64, device=dev) for k in ("diag", "diag_se", "closeness")}
+    out.update({k: torch.empty(1, dtype=torch.float64, device=dev) for k in ("trace", "kemeny", "kemeny_se")})
+    stream = torch.cuda.current_stream()
+
+    def step():
+        g.estimate(omega, seed, root, B=64, out=out, stream=stream)
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    st = g.last_stats()
+    lap.prof_reset()
+    lap.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"step {i + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lap.prof_enable(False)
+    st = g.last_stats()
+    steps_per = st["wilson_steps"] + st["absorbed_steps"]
+    value = steps_per * args.steps / dt
+    ms_w, n_w = lap.prof_read("wilson_wave")
+    ms_a, n_a = lap.prof_read("absorbed")
+    ms_s, n_s = lap.prof_read("assemble")
+    wave_ms = ms_w / max(n_w, 1)
+    alg_bytes = WILSON_BYTES_PER_STEP * st["wilson_steps"] + RETRACE_BYTES_PER_NODE * g.n * st["trees"]
+    achieved = alg_bytes / (wave_ms * 1e-3) / 1e9
+    res = {
+        "metric": "walk steps/s & spanning trees/s at 1 GPU, batched vs plain; p99 query latency",
+        "value": value,
+        "unit": "walk steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64 counts, f64 estimates",
+        "data": "synthetic (seeded Barabasi-Albert graph; no dataset)",
+        "config": {"workload": "plain LEWalk closeness + Kemeny: Barabasi-Albert n=100000 m=5, "
+                               "root=max degree, omega=4096 trees, Philox seed 1",
+                   "n": g.n, "nnz": g.nnz, "omega": omega, "mode": "wave"},
+        "trees_per_s": omega * args.steps / dt,
+        "wilson_steps_per_step": st["wilson_steps"],
+        "absorbed_steps_per_step": st["absorbed_steps"],
+        "kernel_ms": {"wilson_wave": wave_ms, "absorbed": ms_a / max(n_a, 1),
+                      "assemble": ms_s / max(n_s, 1)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "wilson_wave_kernel",
+                     "bytes_per_launch": alg_bytes},
+        "estimates": {"kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item()),
+                      "trace_Ldagger": float(out["trace"].item())},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        from oracle import csr as ocsr
+        og = ocsr.build_csr(n, src, dst)
+        res["cpu_baseline"] = cpu_baseline(og, root, omega, seed)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

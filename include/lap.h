@@ -1,0 +1,197 @@
+/*
+ * lap.h -- C ABI of the MI355X loop-erased-walk library.
+ *
+ * Estimates the diagonal of the Laplacian pseudo-inverse L^dagger, electrical
+ * closeness centrality and Kemeny's constant of a simple undirected connected
+ * graph from Wilson loop-erased-walk samples rooted at a landmark v plus
+ * v-absorbed walks, following "Scalable Algorithms for Laplacian
+ * Pseudo-inverse Computation" (arXiv 2311.10290):
+ *   - problem statement: Sec. 2 (input graph, L^dagger, closeness, Kemeny);
+ *   - estimators: LEWalk for closeness (Alg. 2) and for Kemeny (Alg. 4);
+ *   - sampling facts they rest on: Lemmas 1, 4, 5 and the Sec. 5 lemma.
+ *
+ * General conventions
+ *   - Every function returns a lap_status; on error the outputs are left
+ *     untouched and lap_last_error() returns a message (thread-local).
+ *   - Host buffers are owned by the caller.  Device memory for the graph and
+ *     for sampling workspace is owned by the lap_graph handle and freed by
+ *     lap_graph_free().  When LAP_OUT_DEVICE is set, output pointers are
+ *     device pointers owned by the caller.
+ *   - Work is enqueued on the given hipStream_t (passed as void*, NULL = the
+ *     null stream) and the call returns after it has completed.
+ *   - A handle is not thread-safe: calls on one handle must not overlap.
+ *   - Limits: 1 <= n < 2^31; node degree < 2^24; 2m < 2^40; omega >= 1.
+ *
+ * Random numbers (the paper leaves the generator open).  All draws come from
+ * Philox4x64-10 with key (seed, stream << 32 | root).  The k-th draw at node
+ * u in Wilson sample i is the stack entry S[u][k] of Wilson's stack picture
+ * (Sec. 3.4), counter (i, u, k, qid); absorbed walk i of kind t (1 = uniform
+ * start, 2 = stationary start) uses counter (i | t << 56, step, 0, qid).  A
+ * draw x picks index floor(x * d / 2^64) among d choices (neighbours in
+ * ascending order, the n nodes, or the 2m CSR slots).  Since Wilson's stacks
+ * do not depend on the order walks are run in, every execution schedule of
+ * the library yields the same integer counts for the same arguments.
+ */
+#ifndef LAP_H
+#define LAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LAP_OK = 0,
+    LAP_EINVAL = -1,    /* bad argument (range, NULL, inconsistent sizes) */
+    LAP_ENOTCONN = -2,  /* graph not connected and LAP_KEEP_LCC not given (L_v singular) */
+    LAP_ENOMEM = -3,    /* host or device allocation failed */
+    LAP_EDEVICE = -4,   /* HIP runtime error, or no device */
+    LAP_ERANGE = -5     /* a count exceeded its field (e.g. 2^24 draws at one node in one
+                           sample) or a kernel passed its time limit */
+} lap_status;
+
+/* ------------------------------------------------------------------ graph */
+
+typedef struct lap_graph lap_graph;
+
+enum { LAP_KEEP_LCC = 1 };
+
+/*
+ * lap_build_csr -- graph preparation (precondition of Sec. 2: simple,
+ * undirected, connected).  src/dst: host arrays of n_edges node ids in
+ * [0, n); each pair is an undirected edge.  Self-loops are dropped and
+ * repeated pairs (in either orientation) merged.  If the result is not
+ * connected: with LAP_KEEP_LCC the largest component is kept (ties: the one
+ * holding the smallest id) and renumbered by ascending original id,
+ * otherwise LAP_ENOTCONN.  Neighbour lists are sorted ascending.  The CSR
+ * (row offsets int64[n+1], columns int32[2m]) is uploaded to the device
+ * current at the call.  *out receives a new handle.
+ */
+int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst,
+                  uint32_t flags, void *hip_stream, lap_graph **out);
+
+/* Sizes of a handle's graph (any pointer may be NULL).  max_deg_node is the
+ * default landmark: the highest-degree node, lowest id on ties (Sec. 6.1). */
+int lap_graph_info(const lap_graph *g, int64_t *n, int64_t *nnz, int32_t *max_deg_node,
+                   int32_t *max_deg);
+
+/* Copy the prepared graph to host arrays rp[n+1], col[nnz] and
+ * old_ids[n] (original id of each node); any pointer may be NULL. */
+int lap_graph_copy_csr(const lap_graph *g, int64_t *rp, int32_t *col, int32_t *old_ids);
+
+/* Release a handle and all device memory it owns.  NULL is ignored. */
+void lap_graph_free(lap_graph *g);
+
+/* --------------------------------------------------------------- sampling */
+
+enum {
+    LAP_WANT_Y1 = 1,          /* Wilson draw counts per node, [B][n] */
+    LAP_WANT_Y2_UNIFORM = 2,  /* uniform-start absorbed walks: visits per node [B][n] and lengths */
+    LAP_WANT_Y2_PI = 4,       /* stationary-start absorbed walks: lengths */
+    LAP_WANT_PER_SAMPLE = 8,  /* total draws of every Wilson sample */
+    LAP_OUT_DEVICE = 16       /* output pointers are device pointers */
+};
+
+enum {
+    LAP_MODE_AUTO = 0,        /* wave-cooperative walker pool */
+    LAP_MODE_LANE = 1,        /* one lane per sample, walks run one after another */
+    LAP_MODE_WAVE = 2         /* one wavefront per sample, 64 concurrent walkers */
+};
+
+typedef struct {
+    int64_t n_samples;     /* omega >= 1: Wilson samples, and walks of each requested kind */
+    uint64_t seed;         /* Philox key word 0 */
+    int32_t root;          /* landmark v; -1 = highest-degree node */
+    uint32_t stream;       /* Philox key word 1 high half */
+    uint64_t qid;          /* Philox counter word 3 */
+    uint32_t want;         /* LAP_WANT_* bits */
+    int32_t n_blocks;      /* B >= 1 contiguous sample blocks for batch-means errors */
+    int64_t sample_begin;  /* index of the first sample (resuming a run) */
+    int64_t n_total;       /* samples of the whole run; block of sample i = floor(i*B/n_total);
+                              0 = sample_begin + n_samples */
+    int32_t mode;          /* LAP_MODE_* */
+    int32_t pool;          /* concurrent samples (slots); 0 = automatic */
+    double timeout_s;      /* kernel time limit; 0 = 120 s */
+} lap_sample_args;
+
+typedef struct {
+    int64_t *y1;             /* [B][n] Wilson draws per node (sum over samples), or NULL */
+    int64_t *y2;             /* [B][n] departures per node of uniform-start walks, or NULL */
+    int64_t *y1_per_sample;  /* [n_samples] total draws of each Wilson sample, or NULL */
+    int64_t *y2len_uniform;  /* [n_samples] length of each uniform-start walk, or NULL */
+    int64_t *y2len_pi;       /* [n_samples] length of each stationary-start walk, or NULL */
+    const int64_t *keep_idx; /* [n_keep] absolute sample indices to export (host array) */
+    int64_t n_keep;          /* <= 64 */
+    int32_t *next;           /* [n_keep][n] tree parent of each node (-1 at the root), or NULL */
+    int32_t *draws;          /* [n_keep][n] draws at each node, or NULL */
+} lap_counts;
+
+/*
+ * lap_sample_forests -- the integer core of Alg. 2 / Alg. 4.
+ * Runs Wilson samples sample_begin .. sample_begin+n_samples-1 rooted at v
+ * (Sec. 3.4) when LAP_WANT_Y1 or LAP_WANT_PER_SAMPLE or n_keep > 0, and the
+ * requested absorbed walks with the same indices.  Counts are exact int64;
+ * departures from a node are counted at every draw, the final arrival at the
+ * tree (or at v) is not.  Outputs not requested may be NULL.
+ */
+int lap_sample_forests(lap_graph *g, const lap_sample_args *a, lap_counts *out, void *hip_stream);
+
+/* ------------------------------------------------------------- estimators */
+
+typedef struct {
+    double *diag;        /* [n] estimate of diag(L^dagger) (Alg. 2 output), or NULL */
+    double *diag_se;     /* [n] batch-means standard error (needs B >= 2), or NULL */
+    double *lv_diag;     /* [n] estimate of (L_v^{-1})_uu, 0 at v, or NULL */
+    double *closeness;   /* [n] c(u) = (n-1)/(Tr + n diag_u) (Sec. 2), or NULL */
+    double *trace;       /* [1] Tr(L^dagger) estimate (Kirchhoff index / n), or NULL */
+    double *kemeny;      /* [1] Kemeny's constant (Alg. 4), or NULL */
+    double *kemeny_se;   /* [1] its standard error from per-sample differences, or NULL */
+} lap_estimates;
+
+/*
+ * lap_estimate -- one pass of the hot path: omega Wilson samples, omega
+ * uniform-start absorbed walks if any of diag/diag_se/closeness/trace is
+ * requested, omega stationary-start walks if kemeny is requested, and the
+ * FP64 assembly on the device:
+ *   diag_u = (Y1_u - 2 Y2_u) / (omega d_u) + (1/n) sum_w Y2_w / (omega d_w)   (Alg. 2)
+ *   kappa  = (sum_i y1_i - sum_i len_i) / omega                               (Alg. 4)
+ * Output pointers are host pointers unless LAP_OUT_DEVICE is set in a->want.
+ */
+int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimates *out, void *hip_stream);
+
+/* Convenience forms of lap_estimate with default arguments (automatic mode,
+ * stream 0, qid 0, B = 64 when se is requested).  root = -1 picks the
+ * highest-degree node.  Host outputs. */
+int lap_diag_Ldagger(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *diag,
+                     double *se, void *hip_stream);
+int lap_ecc(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *c,
+            double *trace_Ldagger, void *hip_stream);
+int lap_kemeny(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *kappa,
+               double *se, void *hip_stream);
+
+/* ---------------------------------------------------------------- support */
+
+/* Message for the last error on this thread ("" if none). */
+const char *lap_last_error(void);
+
+/* Kernel timing: when enabled, every kernel launch of the library is
+ * bracketed by HIP events on the stream it runs on; lap_prof_read returns
+ * the accumulated milliseconds and launch count for a kernel name
+ * ("wilson_wave", "wilson_lane", "absorbed", "assemble").  Returns
+ * LAP_EINVAL for an unknown name. */
+int lap_prof_enable(int on);
+int lap_prof_reset(void);
+int lap_prof_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/* Counters of the last lap_sample_forests / lap_estimate call: Wilson walk
+ * steps (draws), absorbed-walk steps, completed trees, wave iterations,
+ * deadlock pops, rescans.  Any pointer may be NULL. */
+int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_steps,
+                   int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAP_H */

@@ -1,0 +1,71 @@
+"""ctypes declarations mirroring include/lap.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblap.so")
+
+LAP_OK, LAP_EINVAL, LAP_ENOTCONN, LAP_ENOMEM, LAP_EDEVICE, LAP_ERANGE = 0, -1, -2, -3, -4, -5
+LAP_KEEP_LCC = 1
+LAP_WANT_Y1, LAP_WANT_Y2_UNIFORM, LAP_WANT_Y2_PI, LAP_WANT_PER_SAMPLE, LAP_OUT_DEVICE = 1, 2, 4, 8, 16
+LAP_MODE_AUTO, LAP_MODE_LANE, LAP_MODE_WAVE = 0, 1, 2
+
+# every symbol include/lap.h declares
+EXPORTS = [
+    "lap_build_csr", "lap_graph_info", "lap_graph_copy_csr", "lap_graph_free",
+    "lap_sample_forests", "lap_estimate", "lap_diag_Ldagger", "lap_ecc", "lap_kemeny",
+    "lap_last_error", "lap_prof_enable", "lap_prof_reset", "lap_prof_read", "lap_last_stats",
+]
+
+
+class SampleArgs(ctypes.Structure):
+    _fields_ = [
+        ("n_samples", ctypes.c_int64), ("seed", ctypes.c_uint64), ("root", ctypes.c_int32),
+        ("stream", ctypes.c_uint32), ("qid", ctypes.c_uint64), ("want", ctypes.c_uint32),
+        ("n_blocks", ctypes.c_int32), ("sample_begin", ctypes.c_int64), ("n_total", ctypes.c_int64),
+        ("mode", ctypes.c_int32), ("pool", ctypes.c_int32), ("timeout_s", ctypes.c_double),
+    ]
+
+
+class Counts(ctypes.Structure):
+    _fields_ = [
+        ("y1", ctypes.c_void_p), ("y2", ctypes.c_void_p), ("y1_per_sample", ctypes.c_void_p),
+        ("y2len_uniform", ctypes.c_void_p), ("y2len_pi", ctypes.c_void_p),
+        ("keep_idx", ctypes.c_void_p), ("n_keep", ctypes.c_int64),
+        ("next", ctypes.c_void_p), ("draws", ctypes.c_void_p),
+    ]
+
+
+class Estimates(ctypes.Structure):
+    _fields_ = [
+        ("diag", ctypes.c_void_p), ("diag_se", ctypes.c_void_p), ("lv_diag", ctypes.c_void_p),
+        ("closeness", ctypes.c_void_p), ("trace", ctypes.c_void_p), ("kemeny", ctypes.c_void_p),
+        ("kemeny_se", ctypes.c_void_p),
+    ]
+
+
+def declare(lib):
+    P, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    sig = {
+        "lap_build_csr": ([i64, i64, P, P, u32, P, P], i32),
+        "lap_graph_info": ([P, P, P, P, P], i32),
+        "lap_graph_copy_csr": ([P, P, P, P], i32),
+        "lap_graph_free": ([P], None),
+        "lap_sample_forests": ([P, ctypes.POINTER(SampleArgs), ctypes.POINTER(Counts), P], i32),
+        "lap_estimate": ([P, ctypes.POINTER(SampleArgs), ctypes.POINTER(Estimates), P], i32),
+        "lap_diag_Ldagger": ([P, i32, i64, u64, P, P, P], i32),
+        "lap_ecc": ([P, i32, i64, u64, P, P, P], i32),
+        "lap_kemeny": ([P, i32, i64, u64, P, P, P], i32),
+        "lap_last_error": ([], ctypes.c_char_p),
+        "lap_prof_enable": ([ctypes.c_int], i32),
+        "lap_prof_reset": ([], i32),
+        "lap_prof_read": ([ctypes.c_char_p, P, P], i32),
+        "lap_last_stats": ([P, P, P, P, P, P, P], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib

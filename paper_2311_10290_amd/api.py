@@ -1,0 +1,198 @@
+"""Python binding of liblap (argument marshalling only).
+
+Graph(n, src, dst)            -> lap_build_csr
+Graph.sample_forests(...)     -> lap_sample_forests   (integer counts)
+Graph.estimate(...)           -> lap_estimate         (diag(L^dagger), closeness, Kemeny)
+diag_Ldagger / ecc / kemeny   -> the convenience entry points
+Outputs are numpy arrays, or caller-supplied torch device tensors when
+``device_out=True``.  ``stream`` is a raw hipStream_t (int) or a torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import _capi as C
+
+
+class LapError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lap status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(C.LIB_PATH):
+            raise ImportError(f"{C.LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python paper_2311_10290_amd/build.py")
+        _lib = C.declare(ctypes.CDLL(C.LIB_PATH))
+    return _lib
+
+
+def _default_timeout():
+    # kernel time limit in seconds (0 = the library default)
+    return float(os.environ.get("LAP_TIMEOUT_S", "0") or 0)
+
+
+def _check(rc):
+    if rc != C.LAP_OK:
+        raise LapError(rc, load_library().lap_last_error().decode())
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())      # torch tensor
+
+
+def prof_enable(on=True):
+    _check(load_library().lap_prof_enable(1 if on else 0))
+
+
+def prof_reset():
+    _check(load_library().lap_prof_reset())
+
+
+def prof_read(kernel):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(load_library().lap_prof_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+class Graph:
+    """A prepared graph resident on the current HIP device (lap_build_csr)."""
+
+    def __init__(self, n, src, dst, keep_lcc=False, stream=None):
+        lib = load_library()
+        src = np.ascontiguousarray(src, np.int32)
+        dst = np.ascontiguousarray(dst, np.int32)
+        if src.shape != dst.shape:
+            raise ValueError("src and dst differ in length")
+        h = ctypes.c_void_p()
+        _check(lib.lap_build_csr(int(n), len(src), _ptr(src), _ptr(dst),
+                                 C.LAP_KEEP_LCC if keep_lcc else 0, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        n_ = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        mdn = ctypes.c_int32()
+        md = ctypes.c_int32()
+        _check(lib.lap_graph_info(h, ctypes.byref(n_), ctypes.byref(nnz), ctypes.byref(mdn), ctypes.byref(md)))
+        self.n, self.nnz, self.max_deg_node, self.max_deg = n_.value, nnz.value, mdn.value, md.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().lap_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def csr(self):
+        rp = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(self.nnz, np.int32)
+        old = np.zeros(self.n, np.int32)
+        _check(load_library().lap_graph_copy_csr(self._h, _ptr(rp), _ptr(col), _ptr(old)))
+        return rp, col, old
+
+    def _args(self, omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s):
+        return C.SampleArgs(n_samples=int(omega), seed=int(seed), root=int(root), stream=int(stream_id),
+                            qid=int(qid), want=int(want), n_blocks=int(B), sample_begin=int(sample_begin),
+                            n_total=int(n_total), mode=int(mode), pool=int(pool),
+                            timeout_s=float(timeout_s) if timeout_s else _default_timeout())
+
+    def sample_forests(self, omega, seed, root=-1, *, y1=True, y2=False, y2_pi=False, per_sample=True,
+                       B=1, keep=(), sample_begin=0, n_total=0, mode=0, pool=0, stream_id=0, qid=0,
+                       timeout_s=0.0, stream=None):
+        """Integer counts of lap_sample_forests as numpy arrays."""
+        n = self.n
+        want = ((C.LAP_WANT_Y1 if y1 else 0) | (C.LAP_WANT_Y2_UNIFORM if y2 else 0)
+                | (C.LAP_WANT_Y2_PI if y2_pi else 0) | (C.LAP_WANT_PER_SAMPLE if per_sample else 0))
+        a = self._args(omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s)
+        keep = np.ascontiguousarray(np.asarray(list(keep), np.int64))
+        nk = len(keep)
+        out = dict(
+            Y1=np.zeros((B, n), np.int64) if y1 else None,
+            Y2=np.zeros((B, n), np.int64) if y2 else None,
+            y1=np.zeros(omega, np.int64) if per_sample else None,
+            len_uniform=np.zeros(omega, np.int64) if y2 else None,
+            len_pi=np.zeros(omega, np.int64) if y2_pi else None,
+            next=np.zeros((nk, n), np.int32) if nk else None,
+            draws=np.zeros((nk, n), np.int32) if nk else None,
+        )
+        c = C.Counts(y1=_ptr(out["Y1"]), y2=_ptr(out["Y2"]), y1_per_sample=_ptr(out["y1"]),
+                     y2len_uniform=_ptr(out["len_uniform"]), y2len_pi=_ptr(out["len_pi"]),
+                     keep_idx=_ptr(keep) if nk else None, n_keep=nk,
+                     next=_ptr(out["next"]), draws=_ptr(out["draws"]))
+        _check(load_library().lap_sample_forests(self._h, ctypes.byref(a), ctypes.byref(c), _stream(stream)))
+        return out
+
+    def estimate(self, omega, seed, root=-1, *, diag=True, se=True, lv=False, closeness=True, kemeny=True,
+                 B=64, mode=0, pool=0, stream_id=0, qid=0, timeout_s=0.0, stream=None, out=None):
+        """FP64 estimates of lap_estimate.  With ``out`` (a dict of torch device
+        tensors: diag, diag_se, lv_diag, closeness [n]; trace, kemeny,
+        kemeny_se [1]) results are written there on the device."""
+        n = self.n
+        dev = out is not None
+        want = C.LAP_OUT_DEVICE if dev else 0
+        a = self._args(omega, seed, root, want, B if se else 1, 0, 0, mode, pool, stream_id, qid, timeout_s)
+        if dev:
+            res = out
+        else:
+            res = dict(
+                diag=np.zeros(n) if diag else None, diag_se=np.zeros(n) if (diag and se) else None,
+                lv_diag=np.zeros(n) if lv else None, closeness=np.zeros(n) if closeness else None,
+                trace=np.zeros(1) if (diag or closeness) else None, kemeny=np.zeros(1) if kemeny else None,
+                kemeny_se=np.zeros(1) if kemeny else None)
+        e = C.Estimates(**{k: _ptr(res.get(k)) for k in
+                           ("diag", "diag_se", "lv_diag", "closeness", "trace", "kemeny", "kemeny_se")})
+        _check(load_library().lap_estimate(self._h, ctypes.byref(a), ctypes.byref(e), _stream(stream)))
+        return res
+
+    def last_stats(self):
+        vals = [ctypes.c_int64() for _ in range(6)]
+        _check(load_library().lap_last_stats(self._h, *[ctypes.byref(v) for v in vals]))
+        keys = ("wilson_steps", "absorbed_steps", "trees", "iterations", "pops", "rescans")
+        return {k: v.value for k, v in zip(keys, vals)}
+
+
+def diag_Ldagger(g: Graph, omega, seed, root=-1, se=True, stream=None):
+    d = np.zeros(g.n)
+    s = np.zeros(g.n) if se else None
+    _check(load_library().lap_diag_Ldagger(g._h, int(root), int(omega), int(seed), _ptr(d), _ptr(s),
+                                           _stream(stream)))
+    return d, s
+
+
+def ecc(g: Graph, omega, seed, root=-1, stream=None):
+    c = np.zeros(g.n)
+    tr = np.zeros(1)
+    _check(load_library().lap_ecc(g._h, int(root), int(omega), int(seed), _ptr(c), _ptr(tr), _stream(stream)))
+    return c, float(tr[0])
+
+
+def kemeny(g: Graph, omega, seed, root=-1, stream=None):
+    k = np.zeros(1)
+    s = np.zeros(1)
+    _check(load_library().lap_kemeny(g._h, int(root), int(omega), int(seed), _ptr(k), _ptr(s), _stream(stream)))
+    return float(k[0]), float(s[0])

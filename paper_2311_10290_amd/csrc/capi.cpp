@@ -1,0 +1,620 @@
+// C ABI of the library (include/lap.h): argument checking, device workspace
+// management, kernel orchestration on the caller's stream, error reporting
+// and optional per-kernel event timing.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lap_host.h"
+#include "lap_launch.h"
+
+using namespace lap;
+
+// ------------------------------------------------------------------- errors
+static thread_local std::string t_err;
+
+static int fail(int code, const std::string &msg) {
+    t_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? LAP_ENOMEM : LAP_EDEVICE,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+extern "C" const char *lap_last_error(void) { return t_err.c_str(); }
+
+// --------------------------------------------------------------- profiling
+namespace {
+struct ProfEntry {
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+struct PendingEvent {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfEntry> g_prof;
+const char *kKernelNames[] = {"wilson_wave", "wilson_lane", "absorbed", "assemble"};
+
+struct Timer {
+    std::vector<PendingEvent> pending;
+    bool on;
+    Timer() {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+    }
+    void begin(const char *name, hipStream_t s) {
+        if (!on) return;
+        PendingEvent p;
+        p.name = name;
+        if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return;
+        (void)hipEventRecord(p.a, s);
+        pending.push_back(p);
+    }
+    void end(hipStream_t s) {
+        if (!on || pending.empty()) return;
+        (void)hipEventRecord(pending.back().b, s);
+    }
+    // call after the streams have been synchronised
+    void collect() {
+        if (!on) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (auto &p : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                g_prof[p.name].ms += ms;
+                g_prof[p.name].launches += 1;
+            }
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        pending.clear();
+    }
+    ~Timer() {
+        for (auto &p : pending) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+    }
+};
+}  // namespace
+
+extern "C" int lap_prof_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return LAP_OK;
+}
+
+extern "C" int lap_prof_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.clear();
+    return LAP_OK;
+}
+
+extern "C" int lap_prof_read(const char *kernel, double *total_ms, int64_t *launches) {
+    if (!kernel) return fail(LAP_EINVAL, "kernel name is NULL");
+    bool known = false;
+    for (const char *k : kKernelNames) known |= std::strcmp(k, kernel) == 0;
+    if (!known) return fail(LAP_EINVAL, std::string("unknown kernel name ") + kernel);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    auto it = g_prof.find(kernel);
+    if (total_ms) *total_ms = it == g_prof.end() ? 0.0 : it->second.ms;
+    if (launches) *launches = it == g_prof.end() ? 0 : it->second.launches;
+    return LAP_OK;
+}
+
+// ------------------------------------------------------------------ buffers
+int DevBuf::ensure(size_t want) {
+    if (want <= bytes && ptr) return LAP_OK;
+    release();
+    if (want == 0) want = 8;
+    if (hipMalloc(&ptr, want) != hipSuccess) {
+        ptr = nullptr;
+        bytes = 0;
+        return LAP_ENOMEM;
+    }
+    bytes = want;
+    return LAP_OK;
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+// ------------------------------------------------------------------- handle
+struct lap_graph {
+    int device = 0;
+    int n_cu = 256;
+    double clock_khz = 100000.0;
+    HostCSR csr;
+    int32_t max_deg_node = 0, max_deg = 0;
+    DevBuf rp, nbr, col;
+    // sampling workspace
+    DevBuf state, epoch;
+    int64_t state_slots = 0;
+    bool state_dirty = false;
+    DevBuf y1, y2, y1s, len_u, len_p, keep_next, keep_draws, err, stats;
+    DevBuf asm_partial, asm_sums, asm_trace, est_out;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int64_t last_stats[kNumStats] = {0};
+    ~lap_graph() {
+        DevBuf *bufs[] = {&rp, &nbr, &col, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
+                          &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out};
+        for (DevBuf *b : bufs) b->release();
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
+};
+
+extern "C" int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst,
+                             uint32_t flags, void *hip_stream, lap_graph **out) {
+    if (!out) return fail(LAP_EINVAL, "out is NULL");
+    if (flags & ~(uint32_t)LAP_KEEP_LCC) return fail(LAP_EINVAL, "unknown flag bits");
+    lap_graph *g = new (std::nothrow) lap_graph();
+    if (!g) return fail(LAP_ENOMEM, "host allocation failed");
+    std::string err;
+    int rc = build_host_csr(n, n_edges, src, dst, (flags & LAP_KEEP_LCC) != 0, g->csr, err);
+    if (rc != LAP_OK) {
+        delete g;
+        return fail(rc, err);
+    }
+    const int64_t nn = g->csr.n, nnz = g->csr.rp[nn];
+    if (nnz >= (int64_t)1 << 40) {
+        delete g;
+        return fail(LAP_ERANGE, "2m must be below 2^40");
+    }
+    std::vector<uint64_t> nbr((size_t)nn);
+    for (int64_t u = 0; u < nn; ++u) {
+        const int64_t d = g->csr.rp[u + 1] - g->csr.rp[u];
+        if (d >= (int64_t)1 << 24) {
+            delete g;
+            return fail(LAP_ERANGE, "node degree must be below 2^24");
+        }
+        if (d > g->max_deg) {
+            g->max_deg = (int32_t)d;
+            g->max_deg_node = (int32_t)u;
+        }
+        nbr[u] = (uint64_t)g->csr.rp[u] | ((uint64_t)d << 40);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete g;
+        return fail(LAP_EDEVICE, "no HIP device");
+    }
+    g->device = dev;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) g->n_cu = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+        g->clock_khz = khz;
+    auto upload = [&](DevBuf &b, const void *src_, size_t bytes) -> int {
+        if (b.ensure(bytes) != LAP_OK) return LAP_ENOMEM;
+        if (bytes && hipMemcpyAsync(b.ptr, src_, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return LAP_EDEVICE;
+        return LAP_OK;
+    };
+    if ((rc = upload(g->rp, g->csr.rp.data(), sizeof(int64_t) * (nn + 1))) != LAP_OK ||
+        (rc = upload(g->nbr, nbr.data(), sizeof(uint64_t) * nn)) != LAP_OK ||
+        (rc = upload(g->col, g->csr.col.data(), sizeof(int32_t) * (size_t)nnz)) != LAP_OK ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        delete g;
+        return fail(rc == LAP_OK ? LAP_EDEVICE : rc, "graph upload failed");
+    }
+    *out = g;
+    return LAP_OK;
+}
+
+extern "C" int lap_graph_info(const lap_graph *g, int64_t *n, int64_t *nnz, int32_t *max_deg_node,
+                              int32_t *max_deg) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (n) *n = g->csr.n;
+    if (nnz) *nnz = g->csr.rp[g->csr.n];
+    if (max_deg_node) *max_deg_node = g->max_deg_node;
+    if (max_deg) *max_deg = g->max_deg;
+    return LAP_OK;
+}
+
+extern "C" int lap_graph_copy_csr(const lap_graph *g, int64_t *rp, int32_t *col, int32_t *old_ids) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (rp) std::memcpy(rp, g->csr.rp.data(), sizeof(int64_t) * g->csr.rp.size());
+    if (col) std::memcpy(col, g->csr.col.data(), sizeof(int32_t) * g->csr.col.size());
+    if (old_ids) std::memcpy(old_ids, g->csr.old_ids.data(), sizeof(int32_t) * g->csr.old_ids.size());
+    return LAP_OK;
+}
+
+extern "C" void lap_graph_free(lap_graph *g) { delete g; }
+
+extern "C" int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_steps,
+                              int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (wilson_steps) *wilson_steps = g->last_stats[kStatDraws];
+    if (absorbed_steps) *absorbed_steps = g->last_stats[kStatAbsorbed];
+    if (trees) *trees = g->last_stats[kStatTrees];
+    if (iterations) *iterations = g->last_stats[kStatIters];
+    if (pops) *pops = g->last_stats[kStatPops];
+    if (rescans) *rescans = g->last_stats[kStatRescans];
+    return LAP_OK;
+}
+
+// --------------------------------------------------------------- sampling
+namespace {
+
+struct Resolved {
+    int64_t omega, begin, total;
+    int32_t root, B, mode;
+    int64_t slots;
+    bool wilson, y2u, y2p;
+};
+
+int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, const int64_t *keep_idx,
+                 Resolved &r) {
+    const int64_t n = g->csr.n;
+    if (!a) return fail(LAP_EINVAL, "args is NULL");
+    if (a->n_samples < 1) return fail(LAP_EINVAL, "n_samples must be >= 1");
+    if (a->root < -1 || a->root >= n) return fail(LAP_EINVAL, "root out of range");
+    if (a->n_blocks < 1) return fail(LAP_EINVAL, "n_blocks must be >= 1");
+    if (a->sample_begin < 0) return fail(LAP_EINVAL, "sample_begin must be >= 0");
+    if (a->mode < LAP_MODE_AUTO || a->mode > LAP_MODE_WAVE) return fail(LAP_EINVAL, "unknown mode");
+    if (a->pool < 0) return fail(LAP_EINVAL, "pool must be >= 0");
+    if (a->want & ~(uint32_t)(LAP_WANT_Y1 | LAP_WANT_Y2_UNIFORM | LAP_WANT_Y2_PI | LAP_WANT_PER_SAMPLE |
+                              LAP_OUT_DEVICE))
+        return fail(LAP_EINVAL, "unknown want bits");
+    r.omega = a->n_samples;
+    r.begin = a->sample_begin;
+    r.total = a->n_total ? a->n_total : a->sample_begin + a->n_samples;
+    if (r.total < r.begin + r.omega) return fail(LAP_EINVAL, "n_total < sample_begin + n_samples");
+    if (r.total >= (int64_t)1 << 56) return fail(LAP_EINVAL, "sample indices must stay below 2^56");
+    if (a->n_blocks > r.total) return fail(LAP_EINVAL, "n_blocks exceeds the number of samples");
+    if (r.total > ((int64_t)1 << 62) / a->n_blocks) return fail(LAP_EINVAL, "n_total * n_blocks too large");
+    if (n_keep < 0 || n_keep > kMaxKeep) return fail(LAP_EINVAL, "n_keep must be in [0, 64]");
+    for (int64_t q = 0; q < n_keep; ++q)
+        if (!keep_idx || keep_idx[q] < r.begin || keep_idx[q] >= r.begin + r.omega)
+            return fail(LAP_EINVAL, "keep_idx entries must be sample indices of this call");
+    r.root = a->root < 0 ? g->max_deg_node : a->root;
+    r.B = a->n_blocks;
+    r.mode = a->mode == LAP_MODE_AUTO ? LAP_MODE_WAVE : a->mode;
+    // concurrent sample slots: bounded by the samples, the pool and a state
+    // budget of 48 GiB (8 bytes per node per slot)
+    const int64_t per_slot = 8 * std::max<int64_t>(n, 1);
+    const int64_t budget = ((int64_t)48 << 30) / per_slot;
+    int64_t pool = a->pool;
+    if (pool == 0) pool = r.mode == LAP_MODE_LANE ? (int64_t)g->n_cu * 256 : (int64_t)g->n_cu * 16;
+    r.slots = std::max<int64_t>(1, std::min({r.omega, pool, budget}));
+    return LAP_OK;
+}
+
+int ensure_state(lap_graph *g, int64_t slots, hipStream_t s) {
+    const int64_t n = g->csr.n;
+    if (slots > g->state_slots || g->state_dirty) {
+        const int64_t alloc = std::max(slots, g->state_slots);
+        const int64_t epoch_words = alloc / 2 + 1;   // 32-bit epochs packed in 64-bit words
+        if (g->state.ensure(sizeof(uint64_t) * (size_t)alloc * n) != LAP_OK ||
+            g->epoch.ensure(sizeof(uint64_t) * (size_t)epoch_words) != LAP_OK)
+            return fail(LAP_ENOMEM, "cannot allocate walk state");
+        HIP_TRY(launch_fill_u64(g->state.as<uint64_t>(), 0ull, alloc * n, s));
+        HIP_TRY(launch_fill_u64(g->epoch.as<uint64_t>(), 0ull, epoch_words, s));
+        g->state_slots = alloc;
+        g->state_dirty = false;
+    }
+    return LAP_OK;
+}
+
+struct RunOut {
+    // device arrays filled by run_sampling (owned by the handle)
+    unsigned long long *y1 = nullptr, *y2 = nullptr;
+    int64_t *y1s = nullptr, *len_u = nullptr, *len_p = nullptr;
+    int32_t *keep_next = nullptr, *keep_draws = nullptr;
+};
+
+int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int64_t n_keep,
+                 const int64_t *keep_idx, bool want_y1, bool want_y1s, RunOut &o, hipStream_t s, Timer &tm) {
+    const int64_t n = g->csr.n;
+    const size_t bn = sizeof(uint64_t) * (size_t)r.B * n;
+    if (g->err.ensure(sizeof(DevErr)) || g->stats.ensure(sizeof(uint64_t) * kNumStats))
+        return fail(LAP_ENOMEM, "cannot allocate workspace");
+    if (want_y1 && g->y1.ensure(bn)) return fail(LAP_ENOMEM, "cannot allocate y1");
+    if (r.y2u && g->y2.ensure(bn)) return fail(LAP_ENOMEM, "cannot allocate y2");
+    if (r.wilson && g->y1s.ensure(sizeof(int64_t) * r.omega)) return fail(LAP_ENOMEM, "cannot allocate y1s");
+    if (r.y2u && g->len_u.ensure(sizeof(int64_t) * r.omega)) return fail(LAP_ENOMEM, "cannot allocate len");
+    if (r.y2p && g->len_p.ensure(sizeof(int64_t) * r.omega)) return fail(LAP_ENOMEM, "cannot allocate len");
+    if (n_keep > 0 && (g->keep_next.ensure(sizeof(int32_t) * n_keep * n) ||
+                       g->keep_draws.ensure(sizeof(int32_t) * n_keep * n)))
+        return fail(LAP_ENOMEM, "cannot allocate kept samples");
+    HIP_TRY(launch_fill_u64(g->err.as<uint64_t>(), 0ull, 1, s));
+    HIP_TRY(launch_fill_u64(g->stats.as<uint64_t>(), 0ull, kNumStats, s));
+    if (want_y1) HIP_TRY(launch_fill_u64(g->y1.as<uint64_t>(), 0ull, (int64_t)r.B * n, s));
+    if (r.y2u) HIP_TRY(launch_fill_u64(g->y2.as<uint64_t>(), 0ull, (int64_t)r.B * n, s));
+
+    const double tmo = a->timeout_s > 0 ? a->timeout_s : 120.0;
+    const uint64_t deadline = (uint64_t)(tmo * g->clock_khz * 1000.0);
+    const uint64_t k1 = ((uint64_t)a->stream << 32) | (uint64_t)(uint32_t)r.root;
+
+    // absorbed walks run on the auxiliary stream, overlapping the Wilson kernel
+    const bool any_walks = r.y2u || r.y2p;
+    if (any_walks) {
+        if (!g->aux) {
+            HIP_TRY(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(g->ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(g->aux, g->ev_fork, 0));
+        for (int kind = 1; kind <= 2; ++kind) {
+            if ((kind == 1 && !r.y2u) || (kind == 2 && !r.y2p)) continue;
+            AbsorbedParams ap;
+            std::memset(&ap, 0, sizeof ap);
+            ap.n = n;
+            ap.nbr = g->nbr.as<uint64_t>();
+            ap.col = g->col.as<int32_t>();
+            ap.nnz = g->csr.rp[n];
+            ap.root = r.root;
+            ap.k0 = a->seed;
+            ap.k1 = k1;
+            ap.qid = a->qid;
+            ap.tag = (uint32_t)kind;
+            ap.walk_begin = r.begin;
+            ap.n_walks = r.omega;
+            ap.n_total = r.total;
+            ap.n_blocks = r.B;
+            ap.y2 = kind == 1 ? g->y2.as<unsigned long long>() : nullptr;
+            ap.len_out = kind == 1 ? g->len_u.as<int64_t>() : g->len_p.as<int64_t>();
+            ap.stats = g->stats.as<unsigned long long>();
+            ap.err = g->err.as<DevErr>();
+            ap.deadline = deadline;
+            tm.begin("absorbed", g->aux);
+            HIP_TRY(launch_absorbed(ap, g->aux));
+            tm.end(g->aux);
+        }
+        HIP_TRY(hipEventRecord(g->ev_join, g->aux));
+    }
+    if (r.wilson) {
+        int rc = ensure_state(g, r.slots, s);
+        if (rc != LAP_OK) return rc;
+        WilsonParams wp;
+        std::memset(&wp, 0, sizeof wp);
+        wp.n = n;
+        wp.nnz = g->csr.rp[n];
+        wp.n_slots = r.slots;   // lanes or waves taking part; <= allocated slots
+        wp.nbr = g->nbr.as<uint64_t>();
+        wp.col = g->col.as<int32_t>();
+        wp.root = r.root;
+        wp.k0 = a->seed;
+        wp.k1 = k1;
+        wp.qid = a->qid;
+        wp.sample_begin = r.begin;
+        wp.n_samples = r.omega;
+        wp.n_total = r.total;
+        wp.n_blocks = r.B;
+        wp.state = g->state.as<uint64_t>();
+        wp.slot_epoch = g->epoch.as<uint32_t>();
+        wp.y1 = want_y1 ? g->y1.as<unsigned long long>() : nullptr;
+        wp.y1_per_sample = g->y1s.as<int64_t>();
+        wp.n_keep = (int32_t)n_keep;
+        for (int64_t q = 0; q < n_keep; ++q) wp.keep_idx[q] = keep_idx[q];
+        wp.next_out = n_keep ? g->keep_next.as<int32_t>() : nullptr;
+        wp.draws_out = n_keep ? g->keep_draws.as<int32_t>() : nullptr;
+        wp.stats = g->stats.as<unsigned long long>();
+        wp.err = g->err.as<DevErr>();
+        wp.deadline = deadline;
+        if (r.mode == LAP_MODE_LANE) {
+            tm.begin("wilson_lane", s);
+            HIP_TRY(launch_wilson_lane(wp, r.slots, s));
+        } else {
+            tm.begin("wilson_wave", s);
+            HIP_TRY(launch_wilson_wave(wp, r.slots, s));
+        }
+        tm.end(s);
+    }
+    (void)want_y1s;
+    if (any_walks) HIP_TRY(hipStreamWaitEvent(s, g->ev_join, 0));
+    o.y1 = want_y1 ? g->y1.as<unsigned long long>() : nullptr;
+    o.y2 = r.y2u ? g->y2.as<unsigned long long>() : nullptr;
+    o.y1s = r.wilson ? g->y1s.as<int64_t>() : nullptr;
+    o.len_u = r.y2u ? g->len_u.as<int64_t>() : nullptr;
+    o.len_p = r.y2p ? g->len_p.as<int64_t>() : nullptr;
+    o.keep_next = n_keep ? g->keep_next.as<int32_t>() : nullptr;
+    o.keep_draws = n_keep ? g->keep_draws.as<int32_t>() : nullptr;
+    return LAP_OK;
+}
+
+// wait for the stream, then turn a device-side error into a status
+int finish(lap_graph *g, hipStream_t s, Timer &tm) {
+    HIP_TRY(hipStreamSynchronize(s));
+    tm.collect();
+    DevErr e{0, 0};
+    uint64_t st[kNumStats];
+    HIP_TRY(hipMemcpy(&e, g->err.ptr, sizeof e, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(st, g->stats.ptr, sizeof st, hipMemcpyDeviceToHost));
+    for (int i = 0; i < kNumStats; ++i) g->last_stats[i] = (int64_t)st[i];
+    if (e.code != kErrNone) {
+        g->state_dirty = true;
+        switch (e.code) {
+            case kErrDrawOverflow:
+                return fail(LAP_ERANGE, "more than 2^24-1 draws at node " + std::to_string(e.detail) +
+                                            " in one sample");
+            case kErrTimeout:
+                return fail(LAP_ERANGE, "kernel time limit exceeded");
+            default:
+                return fail(LAP_EDEVICE, "walker state inconsistent (tree count " +
+                                             std::to_string(e.detail) + ")");
+        }
+    }
+    return LAP_OK;
+}
+
+int copy_out(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (!dst || !bytes) return LAP_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s));
+    return LAP_OK;
+}
+
+}  // namespace
+
+extern "C" int lap_sample_forests(lap_graph *g, const lap_sample_args *a, lap_counts *out, void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (!out) return fail(LAP_EINVAL, "out is NULL");
+    Resolved r;
+    int rc = resolve_args(g, a, out->n_keep, out->keep_idx, r);
+    if (rc != LAP_OK) return rc;
+    const bool want_y1 = (a->want & LAP_WANT_Y1) && out->y1;
+    r.wilson = want_y1 || ((a->want & LAP_WANT_PER_SAMPLE) && out->y1_per_sample) || out->n_keep > 0;
+    r.y2u = (a->want & LAP_WANT_Y2_UNIFORM) && (out->y2 || out->y2len_uniform);
+    r.y2p = (a->want & LAP_WANT_Y2_PI) && out->y2len_pi;
+    hipStream_t s = (hipStream_t)hip_stream;
+    Timer tm;
+    RunOut o;
+    rc = run_sampling(g, r, a, out->n_keep, out->keep_idx, want_y1, true, o, s, tm);
+    if (rc != LAP_OK) return rc;
+    rc = finish(g, s, tm);
+    if (rc != LAP_OK) return rc;
+    const int64_t n = g->csr.n;
+    const size_t bn = sizeof(int64_t) * (size_t)r.B * n;
+    if (want_y1 && (rc = copy_out(out->y1, o.y1, bn, s))) return rc;
+    if (r.y2u && out->y2 && (rc = copy_out(out->y2, o.y2, bn, s))) return rc;
+    if (r.wilson && (a->want & LAP_WANT_PER_SAMPLE) &&
+        (rc = copy_out(out->y1_per_sample, o.y1s, sizeof(int64_t) * r.omega, s)))
+        return rc;
+    if (r.y2u && (rc = copy_out(out->y2len_uniform, o.len_u, sizeof(int64_t) * r.omega, s))) return rc;
+    if (r.y2p && (rc = copy_out(out->y2len_pi, o.len_p, sizeof(int64_t) * r.omega, s))) return rc;
+    if (out->n_keep > 0) {
+        if ((rc = copy_out(out->next, o.keep_next, sizeof(int32_t) * out->n_keep * n, s))) return rc;
+        if ((rc = copy_out(out->draws, o.keep_draws, sizeof(int32_t) * out->n_keep * n, s))) return rc;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return LAP_OK;
+}
+
+extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimates *out, void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (!out) return fail(LAP_EINVAL, "out is NULL");
+    Resolved r;
+    int rc = resolve_args(g, a, 0, nullptr, r);
+    if (rc != LAP_OK) return rc;
+    if (r.begin != 0 || r.total != r.omega)
+        return fail(LAP_EINVAL, "lap_estimate runs a whole sample set: sample_begin = 0, n_total = n_samples");
+    const bool want_diag = out->diag || out->diag_se || out->lv_diag || out->closeness || out->trace;
+    const bool want_kem = out->kemeny || out->kemeny_se;
+    if (!want_diag && !want_kem) return LAP_OK;
+    r.wilson = true;
+    r.y2u = want_diag;
+    r.y2p = want_kem;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = g->csr.n;
+    Timer tm;
+    RunOut o;
+    rc = run_sampling(g, r, a, 0, nullptr, want_diag, true, o, s, tm);
+    if (rc != LAP_OK) return rc;
+    // FP64 assembly on the device into handle-owned buffers
+    const int32_t parts = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 1023) / 1024));
+    if (g->asm_partial.ensure(sizeof(double) * (size_t)(r.B + 1) * parts) ||
+        g->asm_sums.ensure(sizeof(double) * (size_t)(r.B + 2)) || g->asm_trace.ensure(sizeof(double) * parts) ||
+        g->est_out.ensure(sizeof(double) * (4 * (size_t)n + 4)))
+        return fail(LAP_ENOMEM, "cannot allocate assembly buffers");
+    double *d_diag = g->est_out.as<double>(), *d_se = d_diag + n, *d_lv = d_se + n, *d_c = d_lv + n;
+    double *d_scal = d_c + n;   // trace, kappa, kappa_se
+    tm.begin("assemble", s);
+    if (want_diag) {
+        AssembleParams ap;
+        std::memset(&ap, 0, sizeof ap);
+        ap.n = n;
+        ap.root = r.root;
+        ap.n_blocks = r.B;
+        ap.omega = r.omega;
+        ap.nbr = g->nbr.as<uint64_t>();
+        ap.y1 = o.y1;
+        ap.y2 = o.y2;
+        ap.partial = g->asm_partial.as<double>();
+        ap.sums = g->asm_sums.as<double>();
+        ap.trace_parts = g->asm_trace.as<double>();
+        ap.diag = d_diag;
+        ap.diag_se = d_se;
+        ap.lv_diag = d_lv;
+        ap.closeness = d_c;
+        ap.trace = d_scal;
+        ap.n_parts = parts;
+        HIP_TRY(launch_assemble_diag(ap, s));
+    }
+    if (want_kem) HIP_TRY(launch_kemeny(o.y1s, o.len_p, r.omega, d_scal + 1, d_scal + 2, s));
+    tm.end(s);
+    rc = finish(g, s, tm);
+    if (rc != LAP_OK) return rc;
+    if (n == 1) {
+        // a single node: every estimate is zero
+        std::vector<double> z(4 * (size_t)n + 4, 0.0);
+        HIP_TRY(hipMemcpy(d_diag, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if ((rc = copy_out(out->diag, d_diag, sizeof(double) * n, s)) ||
+        (rc = copy_out(out->diag_se, d_se, sizeof(double) * n, s)) ||
+        (rc = copy_out(out->lv_diag, d_lv, sizeof(double) * n, s)) ||
+        (rc = copy_out(out->closeness, d_c, sizeof(double) * n, s)) ||
+        (rc = copy_out(out->trace, d_scal, sizeof(double), s)) ||
+        (rc = copy_out(out->kemeny, d_scal + 1, sizeof(double), s)) ||
+        (rc = copy_out(out->kemeny_se, d_scal + 2, sizeof(double), s)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return LAP_OK;
+}
+
+static lap_sample_args default_args(int32_t root, int64_t omega, uint64_t seed, int32_t B) {
+    lap_sample_args a;
+    std::memset(&a, 0, sizeof a);
+    a.n_samples = omega;
+    a.seed = seed;
+    a.root = root;
+    a.n_blocks = B;
+    return a;
+}
+
+extern "C" int lap_diag_Ldagger(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *diag,
+                                double *se, void *hip_stream) {
+    const int32_t B = se ? (int32_t)std::min<int64_t>(64, std::max<int64_t>(omega, 1)) : 1;
+    lap_sample_args a = default_args(root, omega, seed, B);
+    lap_estimates e;
+    std::memset(&e, 0, sizeof e);
+    e.diag = diag;
+    e.diag_se = se;
+    if (!diag && !se) return fail(LAP_EINVAL, "no output requested");
+    return lap_estimate(g, &a, &e, hip_stream);
+}
+
+extern "C" int lap_ecc(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *c,
+                       double *trace_Ldagger, void *hip_stream) {
+    lap_sample_args a = default_args(root, omega, seed, 1);
+    lap_estimates e;
+    std::memset(&e, 0, sizeof e);
+    e.closeness = c;
+    e.trace = trace_Ldagger;
+    if (!c && !trace_Ldagger) return fail(LAP_EINVAL, "no output requested");
+    return lap_estimate(g, &a, &e, hip_stream);
+}
+
+extern "C" int lap_kemeny(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *kappa, double *se,
+                          void *hip_stream) {
+    lap_sample_args a = default_args(root, omega, seed, 1);
+    lap_estimates e;
+    std::memset(&e, 0, sizeof e);
+    e.kemeny = kappa;
+    e.kemeny_se = se;
+    if (!kappa && !se) return fail(LAP_EINVAL, "no output requested");
+    return lap_estimate(g, &a, &e, hip_stream);
+}

@@ -1,0 +1,34 @@
+// Host-side internals of the library: graph handle, workspace, ingest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lap.h"
+
+namespace lap {
+
+struct HostCSR {
+    int64_t n = 0;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> col;
+    std::vector<int32_t> old_ids;
+};
+
+int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst, bool keep_lcc,
+                   HostCSR &out, std::string &err);
+
+// A device allocation that only grows.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t want);
+    void release();
+    template <class T>
+    T *as() const { return static_cast<T *>(ptr); }
+};
+
+}  // namespace lap

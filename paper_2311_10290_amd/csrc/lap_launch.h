@@ -1,0 +1,41 @@
+// Host-side launchers of the library's kernels (one per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lap_device.h"
+
+namespace lap {
+
+hipError_t launch_wilson_lane(const WilsonParams &p, int64_t slots, hipStream_t s);
+hipError_t launch_wilson_wave(const WilsonParams &p, int64_t slots, hipStream_t s);
+hipError_t launch_absorbed(const AbsorbedParams &p, hipStream_t s);
+
+// Fill n 64-bit words with a value (used instead of hipMemsetAsync so the
+// work can sit inside captured graphs).
+hipError_t launch_fill_u64(uint64_t *dst, uint64_t value, int64_t n, hipStream_t s);
+
+struct AssembleParams {
+    int64_t n;
+    int32_t root;
+    int32_t n_blocks;
+    int64_t omega;                 // samples of the run (sample i -> block floor(i*B/omega))
+    const uint64_t *nbr;           // for degrees
+    const unsigned long long *y1;  // [B][n]
+    const unsigned long long *y2;  // [B][n]
+    double *partial;               // [(B+1) * n_parts] scratch
+    double *sums;                  // [B+1]: sum_w Y2_b[w]/d_w, index B = all blocks
+    double *trace_parts;           // [n_parts] scratch
+    double *diag, *diag_se, *lv_diag, *closeness, *trace;   // outputs (device), each may be null
+    int32_t n_parts;
+};
+
+hipError_t launch_assemble_diag(const AssembleParams &p, hipStream_t s);
+
+// Kemeny's constant from per-sample Wilson totals and stationary-start walk
+// lengths: kappa = (sum y1 - sum len) / omega and its standard error.
+hipError_t launch_kemeny(const int64_t *y1, const int64_t *len, int64_t omega, double *kappa,
+                         double *se, hipStream_t s);
+
+}  // namespace lap
