@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WILSON_BYTES_PER_STEP = 33.0     # offsets 16 + column 4 + draw count 8 + next 4 + tree flag 1
 RETRACE_BYTES_PER_NODE = 5.0
+LOADS_PER_WILSON_STEP = 3        # dependent random loads per draw: column, target state, target offsets
 
 
 def log(msg):
@@ -52,6 +53,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--omega", type=int, default=4096)
+    ap.add_argument("--no-gather", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of 1 GiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -66,6 +70,13 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 8}), flush=True)
+        return
     n, m, omega, seed = 100_000, 5, args.omega, 1
     log("generating BA(100000, 5)")
     src, dst = gg.barabasi_albert(n, m, 0)
@@ -130,6 +141,20 @@ def main():
         "estimates": {"kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item()),
                       "trace_Ldagger": float(out["trace"].item())},
     }
+    if not args.no_gather:
+        log("random-gather peak")
+        lanes = 256 * 24 * 64
+        peaks = {}
+        for label, nbytes in (("4MiB", 4 << 20), ("128MiB", 128 << 20), ("4GiB", 4 << 30)):
+            peaks[label] = {"chase": lap.bench_gather(nbytes, lanes, 1),
+                            "independent": lap.bench_gather(nbytes, lanes // 4, 0)}
+        loads = LOADS_PER_WILSON_STEP * st["wilson_steps"]
+        achieved_loads = loads / (wave_ms * 1e-3)
+        res["gather"] = {"loads_per_wilson_step": LOADS_PER_WILSON_STEP,
+                         "achieved_loads_per_s": achieved_loads,
+                         "peak_loads_per_s": peaks,
+                         "frac_of_chase_peak_4GiB": achieved_loads / peaks["4GiB"]["chase"],
+                         "state_bytes": 8 * g.n * min(omega, 4096)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         from oracle import csr as ocsr

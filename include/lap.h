@@ -190,6 +190,14 @@ int lap_prof_read(const char *kernel, double *total_ms, int64_t *launches);
 int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_steps,
                    int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans);
 
+/* Random-gather peak of the current device, the roofline reference for the
+ * walkers: loads per second (written to *rate) of random 8-byte loads over a
+ * working set of `bytes` (>= 1 MiB, rounded down to a power of two) by
+ * `lanes` (>= 64) concurrent lanes; mode 0 = independent loads, 1 = each
+ * lane follows a dependent pointer chain through a random cyclic order of
+ * 64-byte lines.  Allocates and frees its own buffer. */
+int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, double *rate, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

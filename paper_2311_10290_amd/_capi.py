@@ -17,6 +17,7 @@ EXPORTS = [
     "lap_build_csr", "lap_graph_info", "lap_graph_copy_csr", "lap_graph_free",
     "lap_sample_forests", "lap_estimate", "lap_diag_Ldagger", "lap_ecc", "lap_kemeny",
     "lap_last_error", "lap_prof_enable", "lap_prof_reset", "lap_prof_read", "lap_last_stats",
+    "lap_bench_gather",
 ]
 
 
@@ -63,6 +64,7 @@ def declare(lib):
         "lap_prof_reset": ([], i32),
         "lap_prof_read": ([ctypes.c_char_p, P, P], i32),
         "lap_last_stats": ([P, P, P, P, P, P, P], i32),
+        "lap_bench_gather": ([i64, i64, i32, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

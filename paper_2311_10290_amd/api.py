@@ -176,6 +176,13 @@ class Graph:
         return {k: v.value for k, v in zip(keys, vals)}
 
 
+def bench_gather(bytes_, lanes, mode, stream=None):
+    """Random 8-byte loads per second over a working set (mode 0 independent, 1 chase)."""
+    r = ctypes.c_double()
+    _check(load_library().lap_bench_gather(int(bytes_), int(lanes), int(mode), ctypes.byref(r), _stream(stream)))
+    return r.value
+
+
 def diag_Ldagger(g: Graph, omega, seed, root=-1, se=True, stream=None):
     d = np.zeros(g.n)
     s = np.zeros(g.n) if se else None

@@ -16,37 +16,21 @@
 // fixed order (per-thread strides, then a tree), so results are reproducible.
 #include "lap_device.h"
 #include "lap_launch.h"
+#include "walks.h"
 
 namespace lap {
 
-__global__ __launch_bounds__(256) void absorbed_kernel(AbsorbedParams p) {
+__global__ __launch_bounds__(64) void absorbed_kernel(AbsorbedParams p) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const uint64_t t0 = wall_clock64();
+    const WalkGraph g{p.nbr, p.col, p.n, p.nnz, p.root, p.k0, p.k1, p.qid};
     unsigned long long steps = 0;
     for (int64_t wi = gid; wi < p.n_walks; wi += stride) {
         const int64_t i = p.walk_begin + wi;
-        const uint64_t c0 = (uint64_t)i | ((uint64_t)p.tag << 56);
-        const uint64_t x0 = philox_w0(c0, 0, 0, p.qid, p.k0, p.k1);
-        int32_t u = (p.tag == 1) ? (int32_t)pick_below(x0, (uint64_t)p.n)
-                                 : p.col[pick_below(x0, (uint64_t)p.nnz)];
-        unsigned long long *y2b =
-            p.y2 ? p.y2 + ((i * (int64_t)p.n_blocks) / p.n_total) * p.n : nullptr;
-        int64_t len = 0;
-        bool stop = false;
-        while (u != p.root) {
-            const uint64_t nb = p.nbr[u];
-            if (y2b) atomicAdd(&y2b[u], 1ull);
-            ++len;
-            const uint64_t x = philox_w0(c0, (uint64_t)len, 0, p.qid, p.k0, p.k1);
-            u = p.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
-            if ((len & 1023) == 0 && (wall_clock64() - t0 > p.deadline || err_set(p.err))) {
-                raise_err(p.err, kErrTimeout, 1);
-                stop = true;
-                break;
-            }
-        }
-        if (stop) break;
+        unsigned long long *y2b = p.y2 ? p.y2 + ((i * (int64_t)p.n_blocks) / p.n_total) * p.n : nullptr;
+        const int64_t len = absorbed_walk(g, p.tag, i, y2b, p.err, t0, p.deadline);
+        if (len < 0) break;
         if (p.len_out) p.len_out[wi] = len;
         steps += (unsigned long long)len;
     }

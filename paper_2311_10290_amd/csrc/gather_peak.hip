@@ -1,0 +1,103 @@
+// Random-gather peak of the device, the roofline the walkers are compared
+// against: walker steps are chains of dependent 4-8 byte loads at random
+// addresses, so neither streaming bandwidth nor MFMA rate bounds them.
+//
+//   independent: every lane issues 8 independent random 8-byte loads per
+//                round (addresses from a hash of lane and round), so the
+//                memory system sees as many requests as it will accept;
+//   chase:       every lane follows its own pointer chain through a random
+//                cyclic order of 64-byte lines (one dependent load per hop),
+//                the access pattern of a walker.
+// Both report loads per second over a working set of the given size, which
+// selects the cache tier (L2 4 MB per XCD, 256 MB Infinity Cache, HBM).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lap_launch.h"
+#include "../../include/lap.h"
+
+namespace lap {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// line i (8 words) holds in word 0 the index of the next line of the chain:
+// next = (a * i + c) mod n_lines with n_lines a power of two, a = 5 mod 8,
+// c odd, a full-period permutation, then scrambled by xor with a mask.
+__global__ void chase_init_kernel(uint64_t *buf, uint64_t n_lines, uint64_t a, uint64_t c) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_lines; i += stride)
+        buf[i * 8] = (a * i + c) & (n_lines - 1);
+}
+
+__global__ __launch_bounds__(256) void chase_kernel(const uint64_t *buf, uint64_t n_lines, int64_t hops,
+                                                    uint64_t *sink) {
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t p = mix64(gid) & (n_lines - 1);
+    for (int64_t h = 0; h < hops; ++h) p = buf[p * 8];
+    if (p == 0xFFFFFFFFFFFFFFFFull) sink[0] = p;
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(const uint64_t *buf, uint64_t n_words, int64_t rounds,
+                                                     uint64_t *sink) {
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t acc = 0;
+    for (int64_t r = 0; r < rounds; ++r) {
+        uint64_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = buf[mix64(gid * 0x9E3779B97F4A7C15ull + (uint64_t)r * 8 + j) & (n_words - 1)];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc ^= v[j];
+    }
+    if (acc == 0x1234567) sink[0] = acc;
+}
+
+}  // namespace lap
+
+using namespace lap;
+
+// bytes: working set (rounded down to a power of two, >= 1 MiB); lanes: number
+// of concurrent lanes; mode 0 = independent gathers, 1 = pointer chase.
+// Returns loads per second in *rate.
+extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, double *rate, void *hip_stream) {
+    if (bytes < (1 << 20) || lanes < 64 || !rate || (mode != 0 && mode != 1)) return LAP_EINVAL;
+    uint64_t words = 1;
+    while (words * 2 * 8 <= (uint64_t)bytes) words *= 2;
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint64_t *buf = nullptr, *sink = nullptr;
+    if (hipMalloc(&buf, words * 8) != hipSuccess) return LAP_ENOMEM;
+    if (hipMalloc(&sink, 64) != hipSuccess) {
+        (void)hipFree(buf);
+        return LAP_ENOMEM;
+    }
+    const uint64_t n_lines = words / 8;
+    int rc = LAP_OK;
+    hipLaunchKernelGGL(chase_init_kernel, dim3(4096), dim3(256), 0, s, buf, n_lines, 0x5DEECE66Dull * 8 + 5,
+                       0x2545F4914F6CDD1Dull | 1ull);
+    const unsigned grid = (unsigned)((lanes + 255) / 256);
+    const int64_t work = mode == 0 ? 64 : 512;   // rounds (x8 loads) or hops per lane
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    for (int rep = 0; rep < 2; ++rep) {           // first pass warms the caches
+        (void)hipEventRecord(a, s);
+        if (mode == 0)
+            hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, s, buf, words, work, sink);
+        else
+            hipLaunchKernelGGL(chase_kernel, dim3(grid), dim3(256), 0, s, buf, n_lines, work, sink);
+        (void)hipEventRecord(b, s);
+    }
+    if (hipEventSynchronize(b) != hipSuccess) rc = LAP_EDEVICE;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    const double loads = (double)grid * 256.0 * (double)work * (mode == 0 ? 8.0 : 1.0);
+    *rate = ms > 0 ? loads / (ms * 1e-3) : 0.0;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(buf);
+    (void)hipFree(sink);
+    return rc;
+}

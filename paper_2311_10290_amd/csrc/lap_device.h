@@ -108,6 +108,27 @@ struct WilsonParams {
     uint64_t deadline;             // wall_clock64() ticks a kernel may run before it stops
 };
 
+// One wave-cooperative Wilson sample (the device function shared by the plain
+// and the batched kernels).
+struct WaveSampleArgs {
+    int64_t n, nnz;
+    const uint64_t *nbr;
+    const int32_t *col;
+    int32_t root;
+    uint64_t k0, k1, qid;
+    int64_t sample;
+    uint64_t *st;                  // this slot's [n] state words
+    uint32_t ep;                   // this sample's epoch bit
+    unsigned long long *y1b;       // [n] counts of this sample's block, or null
+    int32_t *keep_next, *keep_draws;   // [n] exports of this sample, or null
+    DevErr *err;
+    uint64_t t0, deadline;
+};
+
+struct WaveStats {
+    unsigned long long iters = 0, draws = 0, trees = 0, pops = 0, rescans = 0;
+};
+
 struct AbsorbedParams {
     int64_t n;
     const uint64_t *nbr;

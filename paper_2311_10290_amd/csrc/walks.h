@@ -1,0 +1,40 @@
+// One v-absorbed walk (the second phase of Alg. 2 for a uniform start, the
+// y2 walk of Alg. 4 for a stationary start), shared by the plain and the
+// batched kernels.  Every departure from a node counts one visit and one unit
+// of length; the arrival at v ends the walk.
+#pragma once
+
+#include "lap_device.h"
+
+namespace lap {
+
+struct WalkGraph {
+    const uint64_t *nbr;
+    const int32_t *col;
+    int64_t n, nnz;
+    int32_t root;
+    uint64_t k0, k1, qid;
+};
+
+// Returns the walk's length, or -1 if the time limit passed (p.err is set).
+static __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag, int64_t i, unsigned long long *y2,
+                                        DevErr *err, uint64_t t0, uint64_t deadline) {
+    const uint64_t c0 = (uint64_t)i | ((uint64_t)tag << 56);
+    const uint64_t x0 = philox_w0(c0, 0, 0, g.qid, g.k0, g.k1);
+    int32_t u = (tag == 1) ? (int32_t)pick_below(x0, (uint64_t)g.n) : g.col[pick_below(x0, (uint64_t)g.nnz)];
+    int64_t len = 0;
+    while (u != g.root) {
+        const uint64_t nb = g.nbr[u];
+        if (y2) atomicAdd(&y2[u], 1ull);
+        ++len;
+        const uint64_t x = philox_w0(c0, (uint64_t)len, 0, g.qid, g.k0, g.k1);
+        u = g.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
+        if ((len & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
+            raise_err(err, kErrTimeout, 1);
+            return -1;
+        }
+    }
+    return len;
+}
+
+}  // namespace lap

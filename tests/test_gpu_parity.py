@@ -152,7 +152,7 @@ def test_convenience_entry_points_agree():
 def test_degenerate_graphs():
     from paper_2311_10290_amd import Graph
     g1 = Graph(1, [], [])
-    e = g1.estimate(8, 1)
+    e = g1.estimate(8, 1, B=4)
     assert (e["diag"] == 0).all() and e["kemeny"][0] == 0.0 and (e["closeness"] == 0).all()
     og, hg = both(2, np.array([0]), np.array([1]))
     got = hg.sample_forests(50, 1, 0, y2=True, y2_pi=True, keep=[3])
