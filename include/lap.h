@@ -170,6 +170,70 @@ int lap_ecc(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *c,
 int lap_kemeny(lap_graph *g, int32_t root, int64_t omega, uint64_t seed, double *kappa,
                double *se, void *hip_stream);
 
+/* --------------------------------------------------------------- batching */
+
+/*
+ * Many independent estimation jobs in one persistent launch.  Each job is
+ * exactly the computation of one lap_estimate call on its own graph (omega
+ * Wilson samples, omega uniform-start and omega stationary-start absorbed
+ * walks, FP64 assembly; Alg. 2 and Alg. 4) with B = 1, and draws the same
+ * Philox stream, so its counts equal those of lap_sample_forests with the
+ * same (seed, stream, qid, root, omega) bit for bit.  The graphs live in one
+ * device arena; resident wavefronts take work items (a chunk of Wilson
+ * samples of one job, or 64 walks of one job) from one atomic counter.
+ */
+typedef struct lap_batch lap_batch;
+
+typedef struct {
+    int64_t n;               /* nodes of the raw edge list */
+    int64_t n_edges;
+    const int32_t *src;      /* host arrays, as for lap_build_csr */
+    const int32_t *dst;
+    uint32_t flags;          /* LAP_KEEP_LCC */
+    int32_t root;            /* -1 = highest-degree node */
+    int64_t n_samples;       /* omega >= 1 */
+    uint64_t seed;
+    uint32_t stream;
+    uint64_t qid;
+} lap_batch_job;
+
+typedef struct {
+    int32_t pool;            /* resident wavefronts; 0 = 16 per compute unit */
+    int32_t chunk_nodes;     /* Wilson samples per work item ~ chunk_nodes / n; 0 = 2^17 */
+    int32_t use_graph;       /* capture the run in a hipGraph once and replay it */
+    double timeout_s;        /* kernel time limit; 0 = 300 s */
+} lap_batch_tuning;
+
+typedef struct {
+    int64_t *y1;             /* [n] Wilson draws per node, or NULL */
+    int64_t *y2;             /* [n] uniform-start walk departures per node, or NULL */
+    int64_t *y1_per_sample;  /* [omega], or NULL */
+    int64_t *y2len_uniform;  /* [omega], or NULL */
+    int64_t *y2len_pi;       /* [omega], or NULL */
+    double *diag;            /* [n] diag(L^dagger) estimate, or NULL */
+    double *closeness;       /* [n], or NULL */
+    double *trace;           /* [1], or NULL */
+    double *kemeny;          /* [1], or NULL */
+    double *kemeny_se;       /* [1], or NULL */
+} lap_batch_out;
+
+/* Prepare every job's graph (as lap_build_csr) into one device arena. */
+int lap_batch_create(const lap_batch_job *jobs, int32_t n_jobs, void *hip_stream, lap_batch **out);
+/* Prepared size and landmark of one job. */
+int lap_batch_job_info(const lap_batch *b, int32_t job, int64_t *n, int64_t *nnz, int32_t *root);
+/* Run all jobs (t may be NULL for defaults); synchronous on hip_stream.  With
+ * use_graph the launch sequence (clears, persistent kernel, assembly) is
+ * captured once per tuning on an internal stream and replayed. */
+int lap_batch_run(lap_batch *b, const lap_batch_tuning *t, void *hip_stream);
+/* Time a grid of pool sizes (8, 16, 24 waves per CU) and chunk sizes (2^15,
+ * 2^17, 2^19) on the whole batch and return the fastest (with use_graph set). */
+int lap_batch_autotune(lap_batch *b, lap_batch_tuning *best, double *best_ms, void *hip_stream);
+/* Copy one job's results of the last run to host buffers (NULL = skip). */
+int lap_batch_result(const lap_batch *b, int32_t job, lap_batch_out *out);
+/* Walk steps and trees of the last run, all jobs together. */
+int lap_batch_stats(const lap_batch *b, int64_t *wilson_steps, int64_t *absorbed_steps, int64_t *trees);
+void lap_batch_free(lap_batch *b);
+
 /* ---------------------------------------------------------------- support */
 
 /* Message for the last error on this thread ("" if none). */
@@ -178,7 +242,8 @@ const char *lap_last_error(void);
 /* Kernel timing: when enabled, every kernel launch of the library is
  * bracketed by HIP events on the stream it runs on; lap_prof_read returns
  * the accumulated milliseconds and launch count for a kernel name
- * ("wilson_wave", "wilson_lane", "absorbed", "assemble").  Returns
+ * ("wilson_wave", "wilson_lane", "absorbed", "assemble", "batch",
+ * "batch_assemble").  Returns
  * LAP_EINVAL for an unknown name. */
 int lap_prof_enable(int on);
 int lap_prof_reset(void);

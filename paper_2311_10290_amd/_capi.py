@@ -18,6 +18,8 @@ EXPORTS = [
     "lap_sample_forests", "lap_estimate", "lap_diag_Ldagger", "lap_ecc", "lap_kemeny",
     "lap_last_error", "lap_prof_enable", "lap_prof_reset", "lap_prof_read", "lap_last_stats",
     "lap_bench_gather",
+    "lap_batch_create", "lap_batch_job_info", "lap_batch_run", "lap_batch_autotune", "lap_batch_result",
+    "lap_batch_stats", "lap_batch_free",
 ]
 
 
@@ -47,6 +49,24 @@ class Estimates(ctypes.Structure):
     ]
 
 
+class BatchJob(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("n_edges", ctypes.c_int64), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32), ("root", ctypes.c_int32), ("n_samples", ctypes.c_int64),
+        ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint32), ("qid", ctypes.c_uint64),
+    ]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("pool", ctypes.c_int32), ("chunk_nodes", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("timeout_s", ctypes.c_double)]
+
+
+class BatchOut(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("y1", "y2", "y1_per_sample", "y2len_uniform", "y2len_pi", "diag",
+                                                "closeness", "trace", "kemeny", "kemeny_se")]
+
+
 def declare(lib):
     P, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
     sig = {
@@ -65,6 +85,13 @@ def declare(lib):
         "lap_prof_read": ([ctypes.c_char_p, P, P], i32),
         "lap_last_stats": ([P, P, P, P, P, P, P], i32),
         "lap_bench_gather": ([i64, i64, i32, P, P], i32),
+        "lap_batch_create": ([ctypes.POINTER(BatchJob), i32, P, P], i32),
+        "lap_batch_job_info": ([P, i32, P, P, P], i32),
+        "lap_batch_run": ([P, ctypes.POINTER(BatchTuning), P], i32),
+        "lap_batch_autotune": ([P, ctypes.POINTER(BatchTuning), P, P], i32),
+        "lap_batch_result": ([P, i32, ctypes.POINTER(BatchOut)], i32),
+        "lap_batch_stats": ([P, P, P, P], i32),
+        "lap_batch_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -176,6 +176,82 @@ class Graph:
         return {k: v.value for k, v in zip(keys, vals)}
 
 
+class Batch:
+    """Many (graph, root, omega) jobs in one persistent launch (lap_batch_*).
+
+    jobs: list of dicts with n, src, dst and optionally keep_lcc, root,
+    omega (n_samples), seed, stream_id, qid."""
+
+    def __init__(self, jobs, stream=None):
+        lib = load_library()
+        self._keep = []
+        arr = (C.BatchJob * len(jobs))()
+        for i, j in enumerate(jobs):
+            s = np.ascontiguousarray(j["src"], np.int32)
+            d = np.ascontiguousarray(j["dst"], np.int32)
+            self._keep += [s, d]
+            arr[i] = C.BatchJob(n=int(j["n"]), n_edges=len(s), src=_ptr(s), dst=_ptr(d),
+                                flags=C.LAP_KEEP_LCC if j.get("keep_lcc") else 0, root=int(j.get("root", -1)),
+                                n_samples=int(j["omega"]), seed=int(j.get("seed", 1)),
+                                stream=int(j.get("stream_id", 0)), qid=int(j.get("qid", 0)))
+        h = ctypes.c_void_p()
+        _check(lib.lap_batch_create(arr, len(jobs), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+        self.n_jobs = len(jobs)
+        self.info = []
+        for i in range(len(jobs)):
+            n = ctypes.c_int64()
+            nnz = ctypes.c_int64()
+            r = ctypes.c_int32()
+            _check(lib.lap_batch_job_info(h, i, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(r)))
+            self.info.append(dict(n=n.value, nnz=nnz.value, root=r.value, omega=int(jobs[i]["omega"])))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().lap_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def tuning(pool=0, chunk_nodes=0, use_graph=True, timeout_s=0.0):
+        return C.BatchTuning(pool=int(pool), chunk_nodes=int(chunk_nodes), use_graph=1 if use_graph else 0,
+                             timeout_s=float(timeout_s) if timeout_s else _default_timeout())
+
+    def run(self, tuning=None, stream=None):
+        t = tuning if tuning is not None else self.tuning()
+        _check(load_library().lap_batch_run(self._h, ctypes.byref(t), _stream(stream)))
+
+    def autotune(self, stream=None):
+        t = C.BatchTuning()
+        ms = ctypes.c_double()
+        _check(load_library().lap_batch_autotune(self._h, ctypes.byref(t), ctypes.byref(ms), _stream(stream)))
+        return t, ms.value
+
+    def result(self, job):
+        inf = self.info[job]
+        n, om = inf["n"], inf["omega"]
+        r = dict(Y1=np.zeros(n, np.int64), Y2=np.zeros(n, np.int64), y1=np.zeros(om, np.int64),
+                 len_uniform=np.zeros(om, np.int64), len_pi=np.zeros(om, np.int64), diag=np.zeros(n),
+                 closeness=np.zeros(n), trace=np.zeros(1), kemeny=np.zeros(1), kemeny_se=np.zeros(1))
+        o = C.BatchOut(y1=_ptr(r["Y1"]), y2=_ptr(r["Y2"]), y1_per_sample=_ptr(r["y1"]),
+                       y2len_uniform=_ptr(r["len_uniform"]), y2len_pi=_ptr(r["len_pi"]), diag=_ptr(r["diag"]),
+                       closeness=_ptr(r["closeness"]), trace=_ptr(r["trace"]), kemeny=_ptr(r["kemeny"]),
+                       kemeny_se=_ptr(r["kemeny_se"]))
+        _check(load_library().lap_batch_result(self._h, int(job), ctypes.byref(o)))
+        return r
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(3)]
+        _check(load_library().lap_batch_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(wilson_steps=v[0].value, absorbed_steps=v[1].value, trees=v[2].value)
+
+
 def bench_gather(bytes_, lanes, mode, stream=None):
     """Random 8-byte loads per second over a working set (mode 0 independent, 1 chase)."""
     r = ctypes.c_double()

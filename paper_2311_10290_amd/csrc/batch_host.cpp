@@ -1,0 +1,373 @@
+// Batched estimation over many graphs (lap_batch_*): graph arena, work-item
+// table, persistent launch (optionally captured in a hipGraph and replayed),
+// per-job results and a small autotuner over the launch parameters.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lap_host.h"
+#include "lap_launch.h"
+
+using namespace lap;
+
+struct lap_batch {
+    int device = 0;
+    int n_cu = 256;
+    double clock_khz = 100000.0;
+    std::vector<BatchJobDev> jobs;
+    std::vector<std::vector<int32_t>> old_ids;
+    int64_t total_n = 0, total_nnz = 0, total_omega = 0, max_n = 0;
+    DevBuf nbr, col, jobs_d, items_d, counter, state, y1, y2, y1s, len_u, len_p, diag, clo, trace, kem, kem_se,
+        err, stats;
+    int64_t state_waves = 0;
+    int64_t n_items = 0;
+    lap_batch_tuning items_for{};        // tuning the item table was built for
+    bool have_items = false;
+    hipStream_t cap = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    lap_batch_tuning exec_for{};
+    int64_t last_stats[kNumStats] = {0};
+    ~lap_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (cap) (void)hipStreamDestroy(cap);
+        DevBuf *b[] = {&nbr, &col, &jobs_d, &items_d, &counter, &state, &y1, &y2, &y1s, &len_u, &len_p,
+                       &diag, &clo, &trace, &kem, &kem_se, &err, &stats};
+        for (DevBuf *x : b) x->release();
+    }
+};
+
+extern "C" int lap_batch_create(const lap_batch_job *jobs, int32_t n_jobs, void *hip_stream, lap_batch **out) {
+    if (!out || !jobs || n_jobs < 1) return fail(LAP_EINVAL, "need jobs and an output handle");
+    lap_batch *b = new (std::nothrow) lap_batch();
+    if (!b) return fail(LAP_ENOMEM, "host allocation failed");
+    std::vector<uint64_t> h_nbr;
+    std::vector<int32_t> h_col;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const lap_batch_job &J = jobs[j];
+        if (J.n_samples < 1 || J.n_samples >= ((int64_t)1 << 56) || (J.flags & ~(uint32_t)LAP_KEEP_LCC)) {
+            delete b;
+            return fail(LAP_EINVAL, "job " + std::to_string(j) + ": bad n_samples or flags");
+        }
+        HostCSR csr;
+        std::string err;
+        int rc = build_host_csr(J.n, J.n_edges, J.src, J.dst, (J.flags & LAP_KEEP_LCC) != 0, csr, err);
+        if (rc != LAP_OK) {
+            delete b;
+            return fail(rc, "job " + std::to_string(j) + ": " + err);
+        }
+        const int64_t n = csr.n, nnz = csr.rp[n];
+        int32_t best = 0;
+        int64_t best_d = -1;
+        for (int64_t u = 0; u < n; ++u) {
+            const int64_t d = csr.rp[u + 1] - csr.rp[u];
+            if (d >= ((int64_t)1 << 24) || nnz >= ((int64_t)1 << 40)) {
+                delete b;
+                return fail(LAP_ERANGE, "job " + std::to_string(j) + ": degree or size beyond the packed fields");
+            }
+            if (d > best_d) {
+                best_d = d;
+                best = (int32_t)u;
+            }
+            h_nbr.push_back((uint64_t)csr.rp[u] | ((uint64_t)d << 40));
+        }
+        if (J.root < -1 || J.root >= n) {
+            delete b;
+            return fail(LAP_EINVAL, "job " + std::to_string(j) + ": root out of range");
+        }
+        BatchJobDev d;
+        std::memset(&d, 0, sizeof d);
+        d.node_off = b->total_n;
+        d.col_off = b->total_nnz;
+        d.n = n;
+        d.nnz = nnz;
+        d.omega = J.n_samples;
+        d.sample_off = b->total_omega;
+        d.root = J.root < 0 ? best : J.root;
+        d.k0 = J.seed;
+        d.k1 = ((uint64_t)J.stream << 32) | (uint64_t)(uint32_t)d.root;
+        d.qid = J.qid;
+        b->jobs.push_back(d);
+        b->old_ids.push_back(std::move(csr.old_ids));
+        h_col.insert(h_col.end(), csr.col.begin(), csr.col.end());
+        b->total_n += n;
+        b->total_nnz += nnz;
+        b->total_omega += J.n_samples;
+        b->max_n = std::max(b->max_n, n);
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&b->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) b->n_cu = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) == hipSuccess && khz > 0)
+        b->clock_khz = khz;
+    const size_t N = (size_t)b->total_n, W = (size_t)b->total_omega, J = b->jobs.size();
+    if (b->nbr.ensure(8 * N) || b->col.ensure(4 * std::max<size_t>(h_col.size(), 1)) ||
+        b->jobs_d.ensure(sizeof(BatchJobDev) * J) || b->counter.ensure(8) || b->y1.ensure(8 * N) ||
+        b->y2.ensure(8 * N) || b->y1s.ensure(8 * W) || b->len_u.ensure(8 * W) || b->len_p.ensure(8 * W) ||
+        b->diag.ensure(8 * N) || b->clo.ensure(8 * N) || b->trace.ensure(8 * J) || b->kem.ensure(8 * J) ||
+        b->kem_se.ensure(8 * J) || b->err.ensure(sizeof(DevErr)) || b->stats.ensure(8 * kNumStats)) {
+        delete b;
+        return fail(LAP_ENOMEM, "cannot allocate batch buffers");
+    }
+    auto up = [&](DevBuf &d, const void *p, size_t bytes) {
+        return bytes ? hipMemcpyAsync(d.ptr, p, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    if (up(b->nbr, h_nbr.data(), 8 * N) != hipSuccess || up(b->col, h_col.data(), 4 * h_col.size()) != hipSuccess ||
+        up(b->jobs_d, b->jobs.data(), sizeof(BatchJobDev) * J) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        delete b;
+        return fail(LAP_EDEVICE, "batch upload failed");
+    }
+    *out = b;
+    return LAP_OK;
+}
+
+extern "C" int lap_batch_job_info(const lap_batch *b, int32_t job, int64_t *n, int64_t *nnz, int32_t *root) {
+    if (!b || job < 0 || job >= (int32_t)b->jobs.size()) return fail(LAP_EINVAL, "bad batch or job index");
+    const BatchJobDev &d = b->jobs[job];
+    if (n) *n = d.n;
+    if (nnz) *nnz = d.nnz;
+    if (root) *root = d.root;
+    return LAP_OK;
+}
+
+namespace {
+
+lap_batch_tuning resolve_tuning(const lap_batch *b, const lap_batch_tuning *t) {
+    lap_batch_tuning r;
+    std::memset(&r, 0, sizeof r);
+    if (t) r = *t;
+    if (r.pool <= 0) r.pool = 16 * b->n_cu;
+    if (r.chunk_nodes <= 0) r.chunk_nodes = 1 << 17;
+    if (r.timeout_s <= 0) r.timeout_s = 300.0;
+    return r;
+}
+
+bool same_shape(const lap_batch_tuning &a, const lap_batch_tuning &c) {
+    return a.pool == c.pool && a.chunk_nodes == c.chunk_nodes && a.timeout_s == c.timeout_s;
+}
+
+// Wilson chunks of about chunk_nodes node-samples, largest graphs first, then
+// 64-walk tiles of both kinds.
+int build_items(lap_batch *b, const lap_batch_tuning &t) {
+    if (b->have_items && b->items_for.chunk_nodes == t.chunk_nodes) return LAP_OK;
+    std::vector<BatchItem> items;
+    std::vector<int32_t> order(b->jobs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return b->jobs[x].n > b->jobs[y].n; });
+    for (int32_t j : order) {
+        const BatchJobDev &d = b->jobs[j];
+        const int64_t per = std::max<int64_t>(1, (int64_t)t.chunk_nodes / std::max<int64_t>(d.n, 1));
+        for (int64_t s = 0; s < d.omega; s += per) items.push_back({j, 0, s, std::min(per, d.omega - s)});
+    }
+    for (int kind = 1; kind <= 2; ++kind)
+        for (int32_t j : order) {
+            const BatchJobDev &d = b->jobs[j];
+            for (int64_t s = 0; s < d.omega; s += 64) items.push_back({j, kind, s, std::min<int64_t>(64, d.omega - s)});
+        }
+    if (b->items_d.ensure(sizeof(BatchItem) * items.size()))
+        return fail(LAP_ENOMEM, "cannot allocate the work-item table");
+    HIP_TRY(hipMemcpy(b->items_d.ptr, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
+    b->n_items = (int64_t)items.size();
+    b->items_for = t;
+    b->have_items = true;
+    return LAP_OK;
+}
+
+BatchParams params(lap_batch *b, const lap_batch_tuning &t) {
+    BatchParams p;
+    std::memset(&p, 0, sizeof p);
+    p.jobs = b->jobs_d.as<BatchJobDev>();
+    p.items = b->items_d.as<BatchItem>();
+    p.n_items = b->n_items;
+    p.counter = b->counter.as<unsigned long long>();
+    p.nbr = b->nbr.as<uint64_t>();
+    p.col = b->col.as<int32_t>();
+    p.state = b->state.as<uint64_t>();
+    p.max_n = b->max_n;
+    p.y1 = b->y1.as<unsigned long long>();
+    p.y2 = b->y2.as<unsigned long long>();
+    p.y1s = b->y1s.as<int64_t>();
+    p.len_u = b->len_u.as<int64_t>();
+    p.len_p = b->len_p.as<int64_t>();
+    p.diag = b->diag.as<double>();
+    p.closeness = b->clo.as<double>();
+    p.trace = b->trace.as<double>();
+    p.kemeny = b->kem.as<double>();
+    p.kemeny_se = b->kem_se.as<double>();
+    p.stats = b->stats.as<unsigned long long>();
+    p.err = b->err.as<DevErr>();
+    p.deadline = (uint64_t)(t.timeout_s * b->clock_khz * 1000.0);
+    return p;
+}
+
+// the whole run as stream work: clear counters and outputs, the persistent
+// kernel, the per-job assembly (fill kernels only, so it can be captured)
+int enqueue_run(lap_batch *b, const lap_batch_tuning &t, hipStream_t s, Timer *tm) {
+    const BatchParams p = params(b, t);
+    HIP_TRY(launch_fill_u64(b->counter.as<uint64_t>(), 0, 1, s));
+    HIP_TRY(launch_fill_u64(b->err.as<uint64_t>(), 0, 1, s));
+    HIP_TRY(launch_fill_u64(b->stats.as<uint64_t>(), 0, kNumStats, s));
+    HIP_TRY(launch_fill_u64(b->y1.as<uint64_t>(), 0, b->total_n, s));
+    HIP_TRY(launch_fill_u64(b->y2.as<uint64_t>(), 0, b->total_n, s));
+    if (tm) tm->begin("batch", s);
+    HIP_TRY(launch_batch(p, t.pool, s));
+    if (tm) {
+        tm->end(s);
+        tm->begin("batch_assemble", s);
+    }
+    HIP_TRY(launch_batch_assemble(p, (int32_t)b->jobs.size(), s));
+    if (tm) tm->end(s);
+    return LAP_OK;
+}
+
+int finish(lap_batch *b, hipStream_t s, Timer &tm) {
+    HIP_TRY(hipStreamSynchronize(s));
+    tm.collect();
+    DevErr e{0, 0};
+    uint64_t st[kNumStats];
+    HIP_TRY(hipMemcpy(&e, b->err.ptr, sizeof e, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(st, b->stats.ptr, sizeof st, hipMemcpyDeviceToHost));
+    for (int i = 0; i < kNumStats; ++i) b->last_stats[i] = (int64_t)st[i];
+    if (e.code == kErrDrawOverflow) return fail(LAP_ERANGE, "more than 2^24-1 draws at one node in one sample");
+    if (e.code == kErrTimeout) return fail(LAP_ERANGE, "batch kernel time limit exceeded");
+    if (e.code != kErrNone) return fail(LAP_EDEVICE, "walker state inconsistent");
+    return LAP_OK;
+}
+
+}  // namespace
+
+extern "C" int lap_batch_run(lap_batch *b, const lap_batch_tuning *tin, void *hip_stream) {
+    if (!b) return fail(LAP_EINVAL, "batch is NULL");
+    const lap_batch_tuning t = resolve_tuning(b, tin);
+    if (t.pool < 1 || t.pool > 64 * b->n_cu) return fail(LAP_EINVAL, "pool out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = build_items(b, t);
+    if (rc != LAP_OK) return rc;
+    if (t.pool > b->state_waves) {
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->state.ensure(8 * (size_t)t.pool * (size_t)b->max_n))
+            return fail(LAP_ENOMEM, "cannot allocate walk state");
+        b->state_waves = t.pool;
+    }
+    Timer tm;
+    if (t.use_graph) {
+        if (!b->cap) {
+            HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+        }
+        if (!b->exec || !same_shape(b->exec_for, t) || b->exec_for.use_graph != t.use_graph) {
+            if (b->exec) (void)hipGraphExecDestroy(b->exec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_run(b, t, b->cap, nullptr);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(b->cap, &g);
+            if (rc != LAP_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            HIP_TRY(ce);
+            b->graph = g;
+            HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            b->exec_for = t;
+        }
+        HIP_TRY(hipEventRecord(b->ev_in, s));
+        HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0));
+        tm.begin("batch", b->cap);
+        HIP_TRY(hipGraphLaunch(b->exec, b->cap));
+        tm.end(b->cap);
+        HIP_TRY(hipEventRecord(b->ev_out, b->cap));
+        HIP_TRY(hipStreamWaitEvent(s, b->ev_out, 0));
+        HIP_TRY(hipStreamSynchronize(b->cap));
+    } else {
+        rc = enqueue_run(b, t, s, &tm);
+        if (rc != LAP_OK) return rc;
+    }
+    return finish(b, s, tm);
+}
+
+extern "C" int lap_batch_autotune(lap_batch *b, lap_batch_tuning *best, double *best_ms, void *hip_stream) {
+    if (!b || !best) return fail(LAP_EINVAL, "batch or output is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int pools[] = {8, 16, 24};
+    const int chunks[] = {1 << 15, 1 << 17, 1 << 19};
+    double best_t = 1e300;
+    lap_batch_tuning bt = resolve_tuning(b, nullptr);
+    hipEvent_t a, c;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&c));
+    int rc = LAP_OK;
+    for (int pw : pools)
+        for (int ch : chunks) {
+            lap_batch_tuning t = resolve_tuning(b, nullptr);
+            t.pool = pw * b->n_cu;
+            t.chunk_nodes = ch;
+            t.use_graph = 0;
+            (void)hipEventRecord(a, s);
+            rc = lap_batch_run(b, &t, hip_stream);
+            (void)hipEventRecord(c, s);
+            if (rc != LAP_OK) break;
+            (void)hipEventSynchronize(c);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, c);
+            if (ms < best_t) {
+                best_t = ms;
+                bt = t;
+            }
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(c);
+    if (rc != LAP_OK) return rc;
+    bt.use_graph = 1;
+    *best = bt;
+    if (best_ms) *best_ms = best_t;
+    return LAP_OK;
+}
+
+extern "C" int lap_batch_result(const lap_batch *b, int32_t job, lap_batch_out *o) {
+    if (!b || !o || job < 0 || job >= (int32_t)b->jobs.size()) return fail(LAP_EINVAL, "bad batch, job or output");
+    const BatchJobDev &d = b->jobs[job];
+    auto get = [&](void *dst, const DevBuf &src, int64_t off, int64_t cnt) -> hipError_t {
+        if (!dst) return hipSuccess;
+        return hipMemcpy(dst, (const char *)src.ptr + 8 * off, 8 * cnt, hipMemcpyDeviceToHost);
+    };
+    HIP_TRY(get(o->y1, b->y1, d.node_off, d.n));
+    HIP_TRY(get(o->y2, b->y2, d.node_off, d.n));
+    HIP_TRY(get(o->y1_per_sample, b->y1s, d.sample_off, d.omega));
+    HIP_TRY(get(o->y2len_uniform, b->len_u, d.sample_off, d.omega));
+    HIP_TRY(get(o->y2len_pi, b->len_p, d.sample_off, d.omega));
+    HIP_TRY(get(o->diag, b->diag, d.node_off, d.n));
+    HIP_TRY(get(o->closeness, b->clo, d.node_off, d.n));
+    HIP_TRY(get(o->trace, b->trace, job, 1));
+    HIP_TRY(get(o->kemeny, b->kem, job, 1));
+    HIP_TRY(get(o->kemeny_se, b->kem_se, job, 1));
+    return LAP_OK;
+}
+
+extern "C" int lap_batch_stats(const lap_batch *b, int64_t *wilson_steps, int64_t *absorbed_steps, int64_t *trees) {
+    if (!b) return fail(LAP_EINVAL, "batch is NULL");
+    if (wilson_steps) *wilson_steps = b->last_stats[kStatDraws];
+    if (absorbed_steps) *absorbed_steps = b->last_stats[kStatAbsorbed];
+    if (trees) *trees = b->last_stats[kStatTrees];
+    return LAP_OK;
+}
+
+extern "C" void lap_batch_free(lap_batch *b) { delete b; }

@@ -146,4 +146,39 @@ struct AbsorbedParams {
     uint64_t deadline;
 };
 
+// ------------------------------------------------------------ batched jobs
+struct BatchJobDev {
+    int64_t node_off;      // first node of the job in the arena (nbr, y1, y2, diag, closeness)
+    int64_t col_off;       // first column entry of the job in the arena
+    int64_t n, nnz, omega;
+    int64_t sample_off;    // first entry of the job in the per-sample arrays
+    int32_t root;
+    int32_t pad;
+    uint64_t k0, k1, qid;  // Philox key and counter word 3
+};
+
+struct BatchItem {
+    int32_t job;
+    int32_t kind;          // 0 Wilson samples, 1 uniform-start walks, 2 stationary-start walks
+    int64_t first, count;
+};
+
+struct BatchParams {
+    const BatchJobDev *jobs;
+    const BatchItem *items;
+    int64_t n_items;
+    unsigned long long *counter;
+    const uint64_t *nbr;   // arena, offsets relative to each job's col_off
+    const int32_t *col;    // arena, job-local node ids
+    uint64_t *state;       // [waves][max_n]
+    int64_t max_n;
+    unsigned long long *y1, *y2;          // [sum n]
+    int64_t *y1s, *len_u, *len_p;         // [sum omega]
+    double *diag, *closeness;             // [sum n]
+    double *trace, *kemeny, *kemeny_se;   // [jobs]
+    unsigned long long *stats;
+    DevErr *err;
+    uint64_t deadline;
+};
+
 }  // namespace lap
