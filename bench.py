@@ -23,6 +23,31 @@ RETRACE_BYTES_PER_NODE = 5.0
 LOADS_PER_WILSON_STEP = 3        # dependent random loads per draw: column, target state, target offsets
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_wave_traffic.json")
+KERNEL_SOURCES = ["paper_2311_10290_amd/csrc/" + f for f in
+                  ("wave_sample.h", "wilson.hip", "lap_device.h")]
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per Wilson launch from the committed counter summary, if it
+    was taken on the current kernel sources; otherwise null."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return t["bytes_per_launch"] if t.get("kernel_hash") == kernel_hash() else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -46,6 +71,58 @@ def cpu_baseline(og, root, omega_full, seed, budget_s=15.0):
             "trees_per_s": n_s / dt}
 
 
+def bench_batch(lap, gg, n_jobs):
+    """Many-graph batch: 512 jobs (half ER with average degree in [8, 20],
+    half BA with m in 2..8, n log-uniform in [1000, 200000], omega uniform in
+    [256, 4096], job list seed 2), each estimating closeness and Kemeny's
+    constant, in one persistent launch; against the same jobs run one by one
+    through the plain path (identical counts, so equal accuracy)."""
+    import torch
+    t0 = time.perf_counter()
+    specs = gg.batch_jobs(n_jobs, seed=2)
+    jobs = []
+    for sp in specs:
+        s, d = gg.job_edges(sp)
+        jobs.append(dict(n=sp["n"], src=s, dst=d, keep_lcc=True, root=-1, omega=sp["omega"], seed=1))
+    log(f"batch: generated {n_jobs} graphs in {time.perf_counter() - t0:.1f} s")
+    b = lap.Batch(jobs)
+    tuning, tune_ms = b.autotune()
+    log(f"batch: autotuned pool={tuning.pool} chunk={tuning.chunk_nodes} ({tune_ms:.1f} ms)")
+    b.run(tuning)
+    torch.cuda.synchronize()
+    reps = 3
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.run(tuning)
+    torch.cuda.synchronize()
+    bt = (time.perf_counter() - t) / reps
+    st = b.stats()
+    steps = st["wilson_steps"] + st["absorbed_steps"]
+    # plain path, one job after another (graph preparation untimed)
+    plain_s = 0.0
+    dev = torch.device("cuda:0")
+    for j, job in enumerate(jobs):
+        g = lap.Graph(job["n"], job["src"], job["dst"], keep_lcc=True)
+        out = {k: torch.empty(g.n, dtype=torch.float64, device=dev) for k in ("diag", "closeness")}
+        out.update({k: torch.empty(1, dtype=torch.float64, device=dev) for k in ("trace", "kemeny", "kemeny_se")})
+        g.estimate(job["omega"], 1, -1, B=1, se=False, out=out)         # warm the workspace
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.estimate(job["omega"], 1, -1, B=1, se=False, out=out)
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t
+        g.close()
+        if (j + 1) % 128 == 0:
+            log(f"batch: plain path {j + 1}/{len(jobs)}")
+    return {"workload": f"{n_jobs} graphs (ER/BA mix, n log-uniform 1e3..2e5, omega 256..4096), one launch",
+            "jobs": n_jobs, "total_nodes": int(sum(i["n"] for i in b.info)),
+            "total_trees": st["trees"], "walk_steps": steps,
+            "batched_s": bt, "batched_steps_per_s": steps / bt, "batched_trees_per_s": st["trees"] / bt,
+            "plain_s": plain_s, "plain_steps_per_s": steps / plain_s, "plain_trees_per_s": st["trees"] / plain_s,
+            "speedup_batched_vs_plain": plain_s / bt,
+            "tuning": {"pool": tuning.pool, "chunk_nodes": tuning.chunk_nodes, "use_graph": tuning.use_graph}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +131,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--omega", type=int, default=4096)
     ap.add_argument("--no-gather", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -131,11 +210,12 @@ def main():
                    "n": g.n, "nnz": g.nnz, "omega": omega, "mode": "wave"},
         "trees_per_s": omega * args.steps / dt,
         "wilson_steps_per_step": st["wilson_steps"],
+        "wave_iterations_per_step": st["iterations"], "cycle_pops": st["pops"], "rescans": st["rescans"],
         "absorbed_steps_per_step": st["absorbed_steps"],
         "kernel_ms": {"wilson_wave": wave_ms, "absorbed": ms_a / max(n_a, 1),
                       "assemble": ms_s / max(n_s, 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "wilson_wave_kernel",
                      "bytes_per_launch": alg_bytes},
         "estimates": {"kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item()),
@@ -155,6 +235,8 @@ def main():
                          "peak_loads_per_s": peaks,
                          "frac_of_chase_peak_4GiB": achieved_loads / peaks["4GiB"]["chase"],
                          "state_bytes": 8 * g.n * min(omega, 4096)}
+    if not args.no_batch:
+        res["batched"] = bench_batch(lap, gg, args.batch_jobs)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         from oracle import csr as ocsr

@@ -131,7 +131,8 @@ __global__ __launch_bounds__(kBA) void batch_assemble_kernel(BatchParams p) {
     __shared__ long long shl[kBA];
     const BatchJobDev jb = p.jobs[blockIdx.x];
     const uint64_t *nbr = p.nbr + jb.node_off;
-    const unsigned long long *y1 = p.y1 + jb.node_off, *y2 = p.y2 + jb.node_off;
+    unsigned long long *y1 = p.y1 + jb.node_off;
+    const unsigned long long *y2 = p.y2 + jb.node_off;
     double *diag = p.diag + jb.node_off, *clo = p.closeness + jb.node_off;
     const double om = (double)jb.omega, nn = (double)jb.n;
     double acc = 0.0;
@@ -141,7 +142,12 @@ __global__ __launch_bounds__(kBA) void batch_assemble_kernel(BatchParams p) {
     double tr = 0.0;
     for (int64_t u = threadIdx.x; u < jb.n; u += kBA) {
         double d = S / (om * nn);
-        if (u != jb.root) d += ((double)y1[u] - 2.0 * (double)y2[u]) / (om * (double)nbr_deg(nbr[u]));
+        if (u != jb.root) {
+            // the kernel counted draws beyond the first; restore the baseline
+            const unsigned long long full = y1[u] + (unsigned long long)jb.omega;
+            y1[u] = full;
+            d += ((double)full - 2.0 * (double)y2[u]) / (om * (double)nbr_deg(nbr[u]));
+        }
         diag[u] = d;
         tr += d;
     }

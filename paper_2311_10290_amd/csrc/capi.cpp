@@ -31,13 +31,13 @@ struct lap_graph {
     int64_t state_slots = 0;
     bool state_dirty = false;
     DevBuf y1, y2, y1s, len_u, len_p, keep_next, keep_draws, err, stats;
-    DevBuf asm_partial, asm_sums, asm_trace, est_out;
+    DevBuf asm_partial, asm_sums, asm_trace, est_out, blkcount;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t last_stats[kNumStats] = {0};
     ~lap_graph() {
         DevBuf *bufs[] = {&rp, &nbr, &col, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
-                          &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out};
+                          &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount};
         for (DevBuf *b : bufs) b->release();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
@@ -365,6 +365,21 @@ extern "C" int lap_sample_forests(lap_graph *g, const lap_sample_args *a, lap_co
     RunOut o;
     rc = run_sampling(g, r, a, out->n_keep, out->keep_idx, want_y1, true, o, s, tm);
     if (rc != LAP_OK) return rc;
+    if (want_y1) {
+        // the kernels count draws beyond the first; add the one-per-sample
+        // baseline: block b holds the samples i of this call with
+        // floor(i*B/n_total) == b
+        std::vector<int64_t> cnt((size_t)r.B);
+        for (int32_t b = 0; b < r.B; ++b) {
+            const int64_t lo = ((int64_t)b * r.total + r.B - 1) / r.B;
+            const int64_t hi = ((int64_t)(b + 1) * r.total + r.B - 1) / r.B;
+            cnt[b] = std::max<int64_t>(0, std::min(hi, r.begin + r.omega) - std::max(lo, r.begin));
+        }
+        if (g->blkcount.ensure(sizeof(int64_t) * r.B)) return fail(LAP_ENOMEM, "cannot allocate block counts");
+        HIP_TRY(hipMemcpyAsync(g->blkcount.ptr, cnt.data(), sizeof(int64_t) * r.B, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_add_baseline(o.y1, g->csr.n, r.root, g->blkcount.as<int64_t>(), r.B, s));
+        HIP_TRY(hipStreamSynchronize(s));   // cnt lives on this stack frame
+    }
     rc = finish(g, s, tm);
     if (rc != LAP_OK) return rc;
     const int64_t n = g->csr.n;

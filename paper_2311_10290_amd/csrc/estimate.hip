@@ -143,7 +143,9 @@ __global__ __launch_bounds__(kAsmBS) void diag_kernel(AssembleParams p) {
             unsigned long long a1 = 0, a2 = 0;
             double m = 0.0, m2 = 0.0;
             for (int b = 0; b < p.n_blocks; ++b) {
-                const unsigned long long c1 = p.y1[(int64_t)b * p.n + u];
+                // counts hold draws beyond the first; add the one-per-sample baseline
+                const unsigned long long c1 =
+                    p.y1[(int64_t)b * p.n + u] + (unsigned long long)block_count(p.omega, p.n_blocks, b);
                 const unsigned long long c2 = p.y2[(int64_t)b * p.n + u];
                 a1 += c1;
                 a2 += c2;
@@ -224,6 +226,26 @@ __global__ __launch_bounds__(kAsmBS) void kemeny_kernel(const int64_t *y1, const
         if (kappa) kappa[0] = mean;
         if (se) se[0] = (omega > 1) ? sqrt(s2 / (double)(omega - 1)) / sqrt((double)omega) : __builtin_nan("");
     }
+}
+
+// Y1[b][u] += count[b] for every u != root: restores full draw counts from
+// the kernels' draws-beyond-the-first.
+__global__ void add_baseline_kernel(unsigned long long *y1, int64_t n, int32_t root, const int64_t *count, int32_t B) {
+    const int64_t total = (int64_t)B * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t u = i % n;
+        if (u != root) y1[i] += (unsigned long long)count[i / n];
+    }
+}
+
+hipError_t launch_add_baseline(unsigned long long *y1, int64_t n, int32_t root, const int64_t *count, int32_t B,
+                               hipStream_t s) {
+    int64_t grid = ((int64_t)B * n + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(add_baseline_kernel, dim3((unsigned)grid), dim3(256), 0, s, y1, n, root, count, B);
+    return hipGetLastError();
 }
 
 hipError_t launch_kemeny(const int64_t *y1, const int64_t *len, int64_t omega, double *kappa, double *se,

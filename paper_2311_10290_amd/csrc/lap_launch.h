@@ -31,6 +31,10 @@ struct AssembleParams {
     int32_t n_parts;
 };
 
+// Y1[b][u] += count[b] for u != root (device array count[B]).
+hipError_t launch_add_baseline(unsigned long long *y1, int64_t n, int32_t root, const int64_t *count, int32_t B,
+                               hipStream_t s);
+
 hipError_t launch_assemble_diag(const AssembleParams &p, hipStream_t s);
 
 // Kemeny's constant from per-sample Wilson totals and stationary-start walk

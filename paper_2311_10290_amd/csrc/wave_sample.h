@@ -1,6 +1,14 @@
-// The wave-cooperative Wilson sample: 64 lanes of one wavefront run
-// concurrent loop-erased walks of one sample (the algorithm is described in
-// wilson.hip).  Included by the plain and the batched kernels.
+// The wave-cooperative Wilson sample: the 64 lanes of one wavefront run
+// concurrent loop-erased walks of one sample (protocol in wilson.hip).
+// Included by the plain and the batched kernels.
+//
+// Each walker keeps its current path -- node ids and their draw counts -- in
+// a small LDS stack, so closing a loop, popping a cycle and joining the tree
+// only write state words (no re-reads), and a draw needs no store at all:
+// other walkers only look at a node's tag, which the claim already wrote.  A
+// path longer than the stack, or a node with more than 255 draws, moves the
+// walker to memory mode: the stack is written out as next/draw words and the
+// walk continues by storing every draw and following next pointers.
 #pragma once
 
 #include "lap_device.h"
@@ -11,8 +19,19 @@ constexpr int kWave = 64;
 constexpr int kClaimBits = 11;
 constexpr int kClaimMask = (1 << kClaimBits) - 1;
 constexpr int kRevCap = 256;
+constexpr int kStackDepth = 12;
+constexpr uint32_t kStackMaxK = 255;
+constexpr int kScanChunks = 4;
 
-enum : int32_t { kIdle = 0, kDraw = 1, kArrive = 2, kRetrace = 3, kRelease = 4, kPopLoad = 5 };
+enum : int32_t {
+    kIdle = 0,
+    kDraw = 1,      // draw at the head h
+    kArrive = 2,    // look at the target w (also: parked, waiting on w)
+    kRetrace = 3,   // memory mode: mark the path s..h as tree, one node per round
+    kRelease = 4,   // memory mode: free the popped nodes x..stop_at, one per round
+    kPopLoad = 5,   // memory mode: load the entry node e of a popped cycle
+    kNbLoad = 6     // stack mode: load the adjacency record of the resumed head
+};
 
 static __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
@@ -24,19 +43,20 @@ static __device__ __forceinline__ int64_t block_of(int64_t sample, int32_t B, in
     return (sample * (int64_t)B) / n_total;
 }
 
-// ----------------------------------------------------------------- wave form
 struct WaveShared {
+    int32_t stk_node[kStackDepth][kWave];
+    uint8_t stk_k[kStackDepth][kWave];
     uint8_t claim_tbl[1 << kClaimBits];
     int32_t rev[kRevCap];
-    int32_t cand[2 * kWave];
+    int32_t cand[kScanChunks * kWave];
     int32_t ent[kWave];
     int32_t mark[kWave];
     int64_t cut_at;
 };
 
-// One Wilson sample run by the calling wavefront's 64 lanes (see the file
-// header).  Returns false when the sample was abandoned (error or time limit;
-// p.err says which); *y1_out receives the sample's total draws.
+// One Wilson sample run by the calling wavefront.  Returns false when the
+// sample was abandoned (error or time limit; c.err says which); *y1_out is
+// the sample's total number of draws.
 static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &sh, int64_t *y1_out, WaveStats &ws) {
     const int lane = (int)threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -44,6 +64,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
     uint64_t *st = c.st;
     const uint32_t ep = c.ep;
     const int64_t sample = c.sample;
+    const uint32_t me = (uint32_t)lane + 1;
     if (lane == 0) {
         st[c.root] = st_pack(-1, 0, kTagTree, ep);
         if (c.keep_next) c.keep_next[c.root] = -1;
@@ -58,11 +79,25 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
     int64_t y1_local = 0;
     int mode = kIdle;
     bool is_start = false;     // the ARRIVE target is a start candidate
-    bool fresh = false;        // mode was set by this iteration's scan
+    bool fresh = false;        // wrote its stack out this round: arrive next round
+    bool mem = false;          // memory mode (path not on the LDS stack)
+    int depth = 0;             // stack entries (stack mode)
     int32_t s = -1, h = -1, w = -1, x = -1, stop_at = -1, e = -1;
     uint32_t kh = 0, ke = 0;
     uint64_t nbh = 0, nbe = 0;
     uint64_t it = 0;
+
+    // write the stack out as path words: entry j points to entry j+1, the top
+    // to top_next (memory mode from here on)
+    auto flush_stack = [&](int32_t top_next) {
+        for (int j = 0; j < depth; ++j) {
+            const int32_t node = sh.stk_node[j][lane];
+            const int32_t nx = (j + 1 < depth) ? sh.stk_node[j + 1][lane] : top_next;
+            st[node] = st_pack(nx, sh.stk_k[j][lane], me, ep);
+        }
+        depth = 0;
+        mem = true;
+    };
 
     while (true) {
         ++it;
@@ -92,50 +127,94 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
             scanning = (n_idle > take) && (cursor < n);
         }
 
-        // ---- 2. one round of loads for every walker (+ the scan)
-        int64_t ld_st = -1, ld_nb = -1, ld_col = -1;
+        // ---- A. first round of loads: draws, memory-mode walks, the scan
+        int64_t la_st = -1, la_nb = -1, la_col = -1;
         if (mode == kDraw) {
             const uint64_t r = philox_w0((uint64_t)sample, (uint64_t)h, kh, c.qid, c.k0, c.k1);
-            ld_col = nbr_off(nbh) + (int64_t)pick_below(r, nbr_deg(nbh));
-        } else if (mode == kArrive) {
-            ld_st = w;
-            ld_nb = w;
+            la_col = nbr_off(nbh) + (int64_t)pick_below(r, nbr_deg(nbh));
         } else if (mode == kRetrace || mode == kRelease) {
-            ld_st = x;
+            la_st = x;
         } else if (mode == kPopLoad) {
-            ld_st = e;
-            ld_nb = e;
+            la_st = e;
+            la_nb = e;
+        } else if (mode == kNbLoad) {
+            la_nb = h;
         }
-        // every index must stay inside the graph; anything else is a bug and
-        // stops the kernel instead of touching memory out of bounds
-        const bool need_st = mode == kArrive || mode == kRetrace || mode == kRelease || mode == kPopLoad;
-        const bool oob = (need_st && (ld_st < 0 || ld_st >= n)) || (ld_nb >= n) ||
-                         (mode == kDraw && (h < 0 || h >= n || ld_col < 0 || ld_col >= c.nnz));
-        if (__ballot(oob)) {
-            if (oob) raise_err(c.err, kErrInconsistent, -1);
-            return false;
+        {
+            // every index must stay inside the graph; anything else is a bug
+            // and stops the kernel instead of touching memory out of bounds
+            const bool oob = ((mode == kRetrace || mode == kRelease || mode == kPopLoad) && (la_st < 0 || la_st >= n)) ||
+                             ((mode == kPopLoad || mode == kNbLoad) && (la_nb < 0 || la_nb >= n)) ||
+                             (mode == kDraw && (h < 0 || h >= n || la_col < 0 || la_col >= c.nnz));
+            if (__ballot(oob)) {
+                if (oob) raise_err(c.err, kErrInconsistent, -1);
+                return false;
+            }
         }
-        const int64_t sc0 = cursor + lane, sc1 = cursor + kWave + lane;
-        const uint64_t v_st = (ld_st >= 0) ? st[ld_st] : 0ull;
-        const uint64_t v_nb = (ld_nb >= 0) ? c.nbr[ld_nb] : 0ull;
-        const int32_t v_col = (ld_col >= 0) ? c.col[ld_col] : 0;
-        const uint64_t v_s0 = (scanning && sc0 < n) ? st[sc0] : 0ull;
-        const uint64_t v_s1 = (scanning && sc1 < n) ? st[sc1] : 0ull;
+        const uint64_t a_st = (la_st >= 0) ? st[la_st] : 0ull;
+        const uint64_t a_nb = (la_nb >= 0) ? c.nbr[la_nb] : 0ull;
+        const int32_t a_col = (la_col >= 0) ? c.col[la_col] : 0;
+        uint64_t v_scan[kScanChunks];
+#pragma unroll
+        for (int q = 0; q < kScanChunks; ++q) {
+            const int64_t sc = cursor + q * kWave + lane;
+            v_scan[q] = (scanning && sc < n) ? st[sc] : 0ull;
+        }
+
+        // ---- 2. finish draws: the drawn neighbour becomes the next target
+        bool bad = false;
+        if (mode == kDraw) {
+            w = a_col;
+            if (kh >= kMaxDraws) {
+                raise_err(c.err, kErrDrawOverflow, h);
+                bad = true;
+            } else if (mem) {
+                st[h] = st_pack(w, kh + 1, me, ep);
+                kh += 1;
+            } else if (kh + 1 > kStackMaxK) {
+                for (int j = 0; j < depth; ++j) {
+                    const int32_t node = sh.stk_node[j][lane];
+                    const int32_t nx = (j + 1 < depth) ? sh.stk_node[j + 1][lane] : w;
+                    const uint32_t kk = (j + 1 < depth) ? sh.stk_k[j][lane] : kh + 1;
+                    st[node] = st_pack(nx, kk, me, ep);
+                }
+                depth = 0;
+                mem = true;
+                kh += 1;
+                fresh = true;      // arrive next round, once the words are visible
+            } else {
+                kh += 1;
+                sh.stk_k[depth - 1][lane] = (uint8_t)kh;
+            }
+            ++ws.draws;
+            mode = kArrive;
+            is_start = false;
+        } else if (mode == kNbLoad) {
+            nbh = a_nb;
+            mode = kDraw;
+        }
 
         // ---- 3. scan: hand FREE candidates to the remaining idle walkers
         if (scanning) {
-            const bool f0 = sc0 < n && st_tag(v_s0, ep) == kTagFree;
-            const bool f1 = sc1 < n && st_tag(v_s1, ep) == kTagFree;
-            const uint64_t m0 = __ballot(f0), m1 = __ballot(f1);
-            const int nf0 = __popcll(m0), nf = nf0 + __popcll(m1);
+            uint64_t m[kScanChunks];
+            int nf = 0;
+#pragma unroll
+            for (int q = 0; q < kScanChunks; ++q) {
+                const int64_t sc = cursor + q * kWave + lane;
+                m[q] = __ballot(sc < n && st_tag(v_scan[q], ep) == kTagFree);
+                nf += __popcll(m[q]);
+            }
             const uint64_t idle2 = __ballot(mode == kIdle);
             const int need = __popcll(idle2);
-            const int q0 = __popcll(m0 & below), q1 = nf0 + __popcll(m1 & below);
-            if (f0 && q0 < need) sh.cand[q0] = (int32_t)sc0;
-            if (f1 && q1 < need) sh.cand[q1] = (int32_t)sc1;
-            if (nf > need) {
-                if (f0 && q0 == need - 1) sh.cut_at = sc0 + 1;
-                if (f1 && q1 == need - 1) sh.cut_at = sc1 + 1;
+            int base = 0;
+#pragma unroll
+            for (int q = 0; q < kScanChunks; ++q) {
+                const bool f = (m[q] >> lane) & 1ull;
+                const int qq = base + __popcll(m[q] & below);
+                const int64_t sc = cursor + q * kWave + lane;
+                if (f && qq < need) sh.cand[qq] = (int32_t)sc;
+                if (f && qq == need - 1 && nf > need) sh.cut_at = sc + 1;
+                base += __popcll(m[q]);
             }
             __syncthreads();
             const int got = min(need, nf);
@@ -145,97 +224,129 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                     w = sh.cand[r];
                     mode = kArrive;
                     is_start = true;
-                    fresh = true;
                 }
             }
-            cursor = (nf > need) ? sh.cut_at : min(n, cursor + 2 * kWave);
+            cursor = (nf > need) ? sh.cut_at : min(n, cursor + kScanChunks * kWave);
         }
 
-        // ---- 4. advance every walker by what its load returned
-        bool claim = false, parked = false, push = false, bad = false;
+        // ---- B. second round of loads: every arriving walker's target
+        const bool arriving = (mode == kArrive) && !fresh;
+        if (arriving && (w < 0 || w >= n)) bad = true;
+        if (__ballot(bad)) {
+            if (bad) raise_err(c.err, kErrInconsistent, -2);
+            return false;
+        }
+        const uint64_t v_st = arriving ? st[w] : a_st;
+        const uint64_t v_nb = arriving ? c.nbr[w] : a_nb;
+
+        // ---- C. advance every walker by what its loads returned
+        bool claim = false, parked = false, push = false;
         int32_t wait_on = lane, pushed = -1;
-        if (!fresh) {
-            if (mode == kDraw) {
-                w = v_col;
-                if (kh >= kMaxDraws) {
-                    raise_err(c.err, kErrDrawOverflow, h);
-                    bad = true;
+        int rel_lo = 0, rel_hi = 0;     // stack entries to release this round
+        if (arriving) {
+            const uint32_t t = st_tag(v_st, ep);
+            if (t == kTagTree) {
+                if (is_start) {
+                    mode = kIdle;
+                } else if (mem) {
+                    mode = kRetrace;   // path s..h joins the tree, one node per round
+                    x = s;
                 } else {
-                    st[h] = st_pack(w, kh + 1, (uint32_t)lane + 1, ep);
-                    kh += 1;
-                    ++ws.draws;
-                }
-                mode = kArrive;
-                is_start = false;
-            } else if (mode == kArrive) {
-                const uint32_t t = st_tag(v_st, ep);
-                if (t == kTagTree) {
-                    if (is_start) {
-                        mode = kIdle;
-                    } else {
-                        mode = kRetrace;   // path s..h joins the tree
-                        x = s;
+                    // the whole path joins the tree now
+                    for (int j = 0; j < depth; ++j) {
+                        const int32_t node = sh.stk_node[j][lane];
+                        const uint32_t k = sh.stk_k[j][lane];
+                        const int32_t nx = (j + 1 < depth) ? sh.stk_node[j + 1][lane] : w;
+                        st[node] = st_pack(nx, k, kTagTree, ep);
+                        if (c.y1b && k > 1) atomicAdd(&c.y1b[node], (unsigned long long)(k - 1));
+                        y1_local += k;
+                        if (c.keep_next) c.keep_next[node] = nx;
+                        if (c.keep_draws) c.keep_draws[node] = (int32_t)k;
                     }
-                } else if (t == (uint32_t)lane + 1 && !is_start) {
-                    // loop closed at w: pop the entries after w, resume at w
+                    tree_local += depth;
+                    depth = 0;
+                    mode = kIdle;
+                }
+            } else if (t == me && !is_start) {
+                // loop closed at w: pop the entries after w, resume at w
+                if (mem) {
                     e = w;
                     ke = st_k(v_st, ep);
                     nbe = v_nb;
                     x = st_next(v_st);
                     stop_at = h;
                     mode = kRelease;
-                } else if (t == kTagFree) {
-                    claim = true;
-                } else if (t <= (uint32_t)kWave) {
-                    if (is_start) {
-                        mode = kIdle;
+                } else {
+                    int p = -1;
+                    for (int j = 0; j < depth; ++j)
+                        if (sh.stk_node[j][lane] == w) p = j;
+                    if (p < 0) {
+                        bad = true;
                     } else {
-                        parked = true;
-                        wait_on = (int32_t)t - 1;
+                        rel_lo = p + 1;
+                        rel_hi = depth;
+                        depth = p + 1;
+                        h = w;
+                        kh = sh.stk_k[p][lane];
+                        nbh = v_nb;
+                        mode = kDraw;
                     }
+                }
+            } else if (t == kTagFree) {
+                claim = true;
+            } else if (t <= (uint32_t)kWave) {
+                if (is_start) {
+                    mode = kIdle;
                 } else {
-                    bad = true;   // a tag no walker of this wave can hold
+                    parked = true;
+                    wait_on = (int32_t)t - 1;
                 }
-            } else if (mode == kRetrace) {
-                const uint32_t k = st_k(v_st, ep);
-                const int32_t nx = st_next(v_st);
-                st[x] = st_pack(nx, k, kTagTree, ep);
-                if (c.y1b) atomicAdd(&c.y1b[x], (unsigned long long)k);
-                y1_local += k;
-                ++tree_local;
-                if (c.keep_next) c.keep_next[x] = nx;
-                if (c.keep_draws) c.keep_draws[x] = (int32_t)k;
-                if (x == h) mode = kIdle;
-                else x = nx;
-            } else if (mode == kRelease) {
-                const int32_t nx = st_next(v_st);
-                st[x] = st_pack(nx, st_k(v_st, ep), kTagFree, ep);
-                if (x < cursor) {
-                    push = true;
-                    pushed = x;
-                }
-                if (x == stop_at) {
-                    h = e;
-                    kh = ke;
-                    nbh = nbe;
-                    mode = kDraw;
-                } else {
-                    x = nx;
-                }
-            } else if (mode == kPopLoad) {
-                ke = st_k(v_st, ep);
-                nbe = v_nb;
-                x = st_next(v_st);
-                stop_at = h;
-                mode = kRelease;
+            } else {
+                bad = true;   // a tag no walker of this wave can hold
             }
+        } else if (mode == kRetrace) {
+            const uint32_t k = st_k(v_st, ep);
+            const int32_t nx = st_next(v_st);
+            st[x] = st_pack(nx, k, kTagTree, ep);
+            if (c.y1b && k > 1) atomicAdd(&c.y1b[x], (unsigned long long)(k - 1));
+            y1_local += k;
+            ++tree_local;
+            if (c.keep_next) c.keep_next[x] = nx;
+            if (c.keep_draws) c.keep_draws[x] = (int32_t)k;
+            if (x == h) {
+                mode = kIdle;
+                mem = false;
+            } else {
+                x = nx;
+            }
+        } else if (mode == kRelease) {
+            const int32_t nx = st_next(v_st);
+            st[x] = st_pack(nx, st_k(v_st, ep), kTagFree, ep);
+            if (x < cursor) {
+                push = true;
+                pushed = x;
+            }
+            if (x == stop_at) {
+                h = e;
+                kh = ke;
+                nbh = nbe;
+                mode = kDraw;
+            } else {
+                x = nx;
+            }
+        } else if (mode == kPopLoad) {
+            ke = st_k(v_st, ep);
+            nbe = v_nb;
+            x = st_next(v_st);
+            stop_at = h;
+            mode = kRelease;
         }
         if (__ballot(bad)) {
-            if (bad) raise_err(c.err, kErrInconsistent, -2);
+            if (bad) raise_err(c.err, kErrInconsistent, -3);
             return false;
         }
 
-        // ---- 5. claims of free nodes, deduplicated through an LDS table
+        // ---- claims of free nodes, deduplicated through an LDS table
         if (claim) sh.claim_tbl[w & kClaimMask] = (uint8_t)lane;
         __syncthreads();
         const int winner = claim ? (int)sh.claim_tbl[w & kClaimMask] : lane;
@@ -243,10 +354,18 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         if (claim) {
             if (winner == lane) {
                 const uint32_t kw = st_k(v_st, ep);
-                st[w] = st_pack(st_current(v_st, ep) ? st_next(v_st) : -1, kw, (uint32_t)lane + 1, ep);
                 if (is_start) {
                     s = w;
                     is_start = false;
+                    mem = false;
+                    depth = 0;
+                }
+                if (!mem && (depth == kStackDepth || kw > kStackMaxK)) flush_stack(w);
+                st[w] = st_pack(-1, kw, me, ep);
+                if (!mem) {
+                    sh.stk_node[depth][lane] = w;
+                    sh.stk_k[depth][lane] = (uint8_t)kw;
+                    ++depth;
                 }
                 h = w;
                 kh = kw;
@@ -263,7 +382,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
             // otherwise a different node hashed to the same slot: retry
         }
 
-        // ---- 6. rings of parked walkers are cycles of stack tops: pop them
+        // ---- rings of parked walkers are cycles of stack tops: pop them
         const uint64_t pk = __ballot(parked);
         if (__popcll(pk) >= 2) {
             const int f = parked ? wait_on : lane;
@@ -280,30 +399,68 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
             if (on_cycle) {
                 e = sh.ent[lane];
                 parked = false;
-                mode = (e == h) ? kDraw : kPopLoad;
+                if (mem) {
+                    mode = (e == h) ? kDraw : kPopLoad;
+                } else {
+                    int p = -1;
+                    for (int j = 0; j < depth; ++j)
+                        if (sh.stk_node[j][lane] == e) p = j;
+                    if (p < 0) {
+                        bad = true;
+                    } else {
+                        rel_lo = p + 1;
+                        rel_hi = depth;
+                        depth = p + 1;
+                        if (e != h) {
+                            h = e;
+                            kh = sh.stk_k[p][lane];
+                            mode = kNbLoad;
+                        } else {
+                            mode = kDraw;
+                        }
+                    }
+                }
             }
             const uint64_t cyc = __ballot(on_cycle);
             if (lane == 0 && cyc) ++ws.pops;
+            if (__ballot(bad)) {
+                if (bad) raise_err(c.err, kErrInconsistent, -4);
+                return false;
+            }
         }
 
-        // ---- 7. released nodes behind the scan go on the revisit list
-        const uint64_t pm = __ballot(push);
-        if (pm) {
-            const int r = __popcll(pm & below);
-            const int cnt = __popcll(pm);
-            if (push && rev_n + r < kRevCap) sh.rev[rev_n + r] = pushed;
-            if (rev_n + cnt > kRevCap) {
-                overflow = true;
-                rev_n = kRevCap;
-            } else {
-                rev_n += cnt;
+        // ---- released nodes: free words; those behind the scan go on the revisit list
+        auto push_round = [&](bool pu, int32_t node) {
+            const uint64_t pm = __ballot(pu);
+            if (pm) {
+                const int r = __popcll(pm & below);
+                const int cnt = __popcll(pm);
+                if (pu && rev_n + r < kRevCap) sh.rev[rev_n + r] = node;
+                if (rev_n + cnt > kRevCap) {
+                    overflow = true;
+                    rev_n = kRevCap;
+                } else {
+                    rev_n += cnt;
+                }
+            }
+        };
+        push_round(push, pushed);
+        if (__ballot(rel_hi > rel_lo)) {
+            for (int j = 0; j < kStackDepth; ++j) {
+                const bool act = j >= rel_lo && j < rel_hi;
+                int32_t node = -1;
+                if (act) {
+                    node = sh.stk_node[j][lane];
+                    st[node] = st_pack(-1, sh.stk_k[j][lane], kTagFree, ep);
+                }
+                push_round(act && node < cursor, node);
             }
         }
         fresh = false;
         __syncthreads();   // stores and LDS writes visible to the next round
         if (lane == 0) ++ws.iters;
 
-        // ---- 8. the sample ends when every node is in the tree
+        // ---- the sample ends when every node is in the tree
         const uint64_t busy = __ballot(mode != kIdle);
         if (!busy && rev_n == 0 && cursor >= n) {
             const int64_t tc = wave_sum_i64(tree_local);

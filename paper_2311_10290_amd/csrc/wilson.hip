@@ -30,9 +30,11 @@
 //                      nodes the scan has already passed.
 //
 // Both keep one packed 64-bit word per node per sample slot in HBM (next,
-// draw count, tag, epoch), add each node's final draw count into the
-// per-block count array when the node joins the tree, and record each
-// sample's total draws.
+// draw count, tag, epoch) and record each sample's total draws.  Every node
+// other than v draws at least once per sample, so when a node joins the tree
+// only its draws beyond the first, k - 1, are added to the per-block count
+// array; the one-per-sample baseline is added back when counts are read out
+// (lap_sample_forests) or assembled.
 #include "lap_device.h"
 #include "lap_launch.h"
 #include "wave_sample.h"
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(64) void wilson_lane_kernel(WilsonParams p) {
                 const uint32_t k = st_k(wy, ep);
                 const int32_t nx = st_next(wy);
                 st[y] = st_pack(nx, k, kTagTree, ep);
-                if (y1b) atomicAdd(&y1b[y], (unsigned long long)k);
+                if (y1b && k > 1) atomicAdd(&y1b[y], (unsigned long long)(k - 1));
                 if (keep_q >= 0) {
                     if (p.next_out) p.next_out[(int64_t)keep_q * n + y] = nx;
                     if (p.draws_out) p.draws_out[(int64_t)keep_q * n + y] = (int32_t)k;
