@@ -9,6 +9,8 @@ absorbed-walk draws) of the whole job.
 """
 import argparse
 import json
+
+import numpy as np
 import math
 import os
 import sys
@@ -123,6 +125,63 @@ def bench_batch(lap, gg, n_jobs):
             "tuning": {"pool": tuning.pool, "chunk_nodes": tuning.chunk_nodes, "use_graph": tuning.use_graph}}
 
 
+def _replay(lap, srv, qs, qid0):
+    """Submit each query at its arrival time (seconds from start), drive the
+    loop, return per-query latencies (completion - submission)."""
+    kinds = {0: lap.Server.CLOSENESS, 1: lap.Server.RESISTANCE, 2: lap.Server.KEMENY}
+    t0 = time.perf_counter()
+    i, out = 0, []
+    while len(out) < len(qs):
+        now = time.perf_counter() - t0
+        while i < len(qs) and qs[i]["t"] <= now:
+            q = qs[i]
+            srv.submit(qid0 + q["qid"], kinds[q["kind"]], q["budget"], q["u"], q["w"])
+            i += 1
+        srv.step(wait=False)
+        out += srv.poll()
+        if i < len(qs) and not srv.pending()["inflight"]:
+            time.sleep(min(0.001, max(0.0, qs[i]["t"] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    lat = np.array([r["t_done"] - r["t_submit"] for r in out])
+    bad = sum(r["status"] != 0 for r in out)
+    return lat, wall, bad
+
+
+def bench_serve(lap, gg, n_queries):
+    """Serving: resident R-MAT scale-21 graph (edge factor 16, a/b/c/d =
+    .57/.19/.19/.05, symmetrised, self-loops and duplicates dropped, largest
+    component); Poisson arrivals mixing single-node closeness (64..1024 walks,
+    log-uniform), pairwise resistance (1024 walk pairs) and Kemeny (256
+    samples) in proportions 45/45/10.  Saturation throughput is measured with
+    every query submitted at once; latency percentiles at 50% and 80% of it."""
+    t = time.perf_counter()
+    src, dst = gg.rmat(21, 16, seed=0)
+    g = lap.Graph(1 << 21, src, dst, keep_lcc=True)
+    del src, dst
+    log(f"serve: R-MAT 21 LCC n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
+    srv = lap.Server(g, seed=1, global_samples=256)
+    qs = gg.query_stream(g.n, n_queries, qps=1.0, seed=3)
+    for q in qs:
+        q["t"] = 0.0
+    lat, wall, bad = _replay(lap, srv, qs, 0)
+    sat = n_queries / wall
+    log(f"serve: saturation {sat:.1f} queries/s")
+    out = {"workload": "R-MAT scale 21 LCC resident; Poisson mix 45% closeness (64-1024 walks), "
+                       "45% resistance (1024 walk pairs), 10% Kemeny (256 samples)",
+           "n": g.n, "nnz": g.nnz, "queries": n_queries, "saturation_qps": sat,
+           "closed_loop_p50_ms": float(np.percentile(lat, 50) * 1e3), "errors": int(bad), "runs": []}
+    for k, frac in enumerate((0.5, 0.8)):
+        qs = gg.query_stream(g.n, n_queries, qps=frac * sat, seed=4 + k)
+        lat, wall, bad = _replay(lap, srv, qs, (k + 1) * 1_000_000)
+        out["runs"].append({"offered_qps": frac * sat, "achieved_qps": n_queries / wall,
+                            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                            "p99_ms": float(np.percentile(lat, 99) * 1e3), "errors": int(bad)})
+        log(f"serve: {frac:.0%} load p50 {out['runs'][-1]['p50_ms']:.1f} ms p99 {out['runs'][-1]['p99_ms']:.1f} ms")
+    srv.close()
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +192,8 @@ def main():
     ap.add_argument("--no-gather", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-jobs", type=int, default=512)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -237,6 +298,8 @@ def main():
                          "state_bytes": 8 * g.n * min(omega, 4096)}
     if not args.no_batch:
         res["batched"] = bench_batch(lap, gg, args.batch_jobs)
+    if not args.no_serve:
+        res["serving"] = bench_serve(lap, gg, args.serve_queries)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         from oracle import csr as ocsr

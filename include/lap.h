@@ -234,6 +234,89 @@ int lap_batch_result(const lap_batch *b, int32_t job, lap_batch_out *out);
 int lap_batch_stats(const lap_batch *b, int64_t *wilson_steps, int64_t *absorbed_steps, int64_t *trees);
 void lap_batch_free(lap_batch *b);
 
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * A request loop over one resident graph.  Query kinds:
+ *   LAP_Q_CLOSENESS  c(u) from `budget` walks started at u and absorbed at v:
+ *                    (L_v^{-1})_uu = E[departures from u]/d_u (Lemma 1) and
+ *                    e_u^T L_v^{-1} 1 = E[sum of 1/d over departures]
+ *                    (normalised-length lemma, Sec. 4.3), combined with the
+ *                    cached Tr(L_v^{-1}) and 1^T L_v^{-1} 1 through the
+ *                    element-wise equation for L^dagger_uu and
+ *                    Tr(L^dagger) = Tr(L_v^{-1}) - 1^T L_v^{-1} 1 / n (Sec. 3.1);
+ *   LAP_Q_RESISTANCE r(u,w) = (L_v^{-1})_uu + (L_v^{-1})_ww - 2 (L_v^{-1})_uw
+ *                    from `budget` pairs of walks from u and from w;
+ *   LAP_Q_KEMENY     Kemeny's constant from `budget` Wilson samples and
+ *                    stationary-start walks (Alg. 4).
+ * Query walk i (sub-stream 0 from u, 1 from w) uses counter
+ * (i | 3<<56, move, sub, qid); a Kemeny query draws exactly what
+ * lap_estimate with qid = the query id and omega = budget draws.  A result
+ * therefore does not depend on which other queries were in flight.
+ *
+ * Scheduling: lap_server_submit queues a query.  lap_server_step retires
+ * finished launches, admits queued queries in arrival order while their
+ * result regions fit in the device result arena (arena_bytes), and starts a
+ * launch on every idle stream with the active queries' next work items, one
+ * per query per round (continuous batching: queries that arrive while
+ * launches are running join the next launch).  Completed queries are
+ * assembled on the host in FP64 and returned by lap_server_poll.
+ */
+typedef struct lap_server lap_server;
+
+enum { LAP_Q_CLOSENESS = 0, LAP_Q_RESISTANCE = 1, LAP_Q_KEMENY = 2 };
+
+/* the query id the server uses for its own cached global terms */
+#define LAP_SERVER_GLOBAL_QID 0xFFFFFFFFFFFFFFFFull
+
+typedef struct {
+    int64_t qid;             /* >= 0; keys the query's random stream */
+    int32_t kind;            /* LAP_Q_* */
+    int32_t u, w;            /* node (closeness), pair (resistance) */
+    int64_t budget;          /* walks, walk pairs or samples */
+} lap_query;
+
+typedef struct {
+    int64_t qid;
+    int32_t kind;
+    int32_t status;          /* LAP_OK, or the error that stopped the query */
+    double value;            /* c(u), r(u,w) or kappa */
+    double se;               /* standard error of value over the query's walks / samples */
+    double t_submit, t_start, t_done;   /* seconds since lap_server_create */
+} lap_query_result;
+
+typedef struct {
+    uint64_t seed;
+    int32_t root;            /* -1 = highest-degree node */
+    uint32_t stream;
+    int64_t global_samples;  /* samples for the cached global terms; 0 = 256 */
+    int64_t arena_bytes;     /* device memory for query results; 0 = 64 MiB */
+    int32_t launches;        /* launches in flight (streams); 0 = 2 */
+    int32_t waves;           /* wavefronts (Wilson state slots) per launch; 0 = 4 per CU */
+    int32_t items_per_launch;/* 0 = 4096 */
+    int32_t wilson_chunk;    /* Wilson samples per work item; 0 = 1 */
+    double timeout_s;        /* kernel time limit; 0 = 300 s */
+} lap_server_config;
+
+/* Compute the cached global terms (lap_sample_forests with qid
+ * LAP_SERVER_GLOBAL_QID) and allocate the arena, the Wilson state of every
+ * launch (launches * waves * n * 8 bytes) and the streams.  The graph must
+ * outlive the server. */
+int lap_server_create(lap_graph *g, const lap_server_config *cfg, void *hip_stream, lap_server **out);
+/* Queue a query (thread-safe).  LAP_ENOMEM if its result region could never
+ * fit in the arena. */
+int lap_server_submit(lap_server *s, const lap_query *q);
+/* Retire, admit and launch (see above); with wait != 0 first block until a
+ * running launch completes. */
+int lap_server_step(lap_server *s, int32_t wait);
+/* Move up to max completed results to out; *n_out receives their number. */
+int lap_server_poll(lap_server *s, lap_query_result *out, int32_t max, int32_t *n_out);
+/* Queries waiting for admission, admitted and not finished, launches running. */
+int lap_server_pending(lap_server *s, int64_t *queued, int64_t *active, int64_t *inflight);
+/* The cached Tr(L_v^{-1}) and 1^T L_v^{-1} 1. */
+int lap_server_globals(const lap_server *s, double *trace_lv, double *sum_lv);
+void lap_server_free(lap_server *s);
+
 /* ---------------------------------------------------------------- support */
 
 /* Message for the last error on this thread ("" if none). */

@@ -59,3 +59,41 @@ def kemeny(y1, y2len):
     est = float(int(y1.sum() - y2.sum())) / omega
     se = float(z.std(ddof=1) / math.sqrt(omega)) if omega > 1 else float("nan")
     return est, se
+
+
+# ----------------------------------------------------------------- queries
+def globals_from_counts(Y1, Y2, omega, deg, root):
+    """Cached global terms for single-node queries:
+    Tr(L_v^{-1}) ~ sum_u Y1[u]/(omega d_u) and 1^T L_v^{-1} 1 ~ n sum_w Y2[w]/(omega d_w)."""
+    deg = np.asarray(deg, np.float64)
+    n = len(deg)
+    mask = np.arange(n) != root
+    tr = math.fsum((np.asarray(Y1, np.float64)[mask] / (omega * deg[mask])).tolist())
+    s = n * math.fsum((np.asarray(Y2, np.float64)[mask] / (omega * deg[mask])).tolist())
+    return tr, s
+
+
+def closeness_query(dep_u, norm_len, d_u, n, tr_lv, s_lv):
+    """c(u) from walks started at u: (L_v^{-1})_uu ~ mean dep_u / d_u (Lemma 1),
+    e_u^T L_v^{-1} 1 ~ mean normalised length (Sec. 4.3 lemma), then the
+    element-wise equation for L^dagger_uu, Tr(L^dagger) = Tr(L_v^{-1}) - S/n and
+    c(u) = (n-1)/(Tr + n L^dagger_uu).  Returns (c, L^dagger_uu, se of L^dagger_uu)."""
+    dep_u = np.asarray(dep_u, np.float64)
+    norm_len = np.asarray(norm_len, np.float64)
+    b = len(dep_u)
+    z = dep_u / d_u - 2.0 * norm_len / n
+    ld = float(math.fsum(z.tolist()) / b) + s_lv / n ** 2
+    tr = tr_lv - s_lv / n
+    c = (n - 1) / (tr + n * ld)
+    se = float(z.std(ddof=1) / math.sqrt(b)) if b > 1 else float("nan")
+    return c, ld, se
+
+
+def resistance_query(ss, st, tt, ts, d_s, d_t):
+    """r(s,t) = (L_v^{-1})_ss + (L_v^{-1})_tt - 2 (L_v^{-1})_st from walk pairs:
+    per pair ss/d_s - st/d_t + tt/d_t - ts/d_s (Lemma 1, both orders of the
+    symmetric off-diagonal term).  Returns (r, se)."""
+    r = (np.asarray(ss, np.float64) / d_s - np.asarray(st, np.float64) / d_t
+         + np.asarray(tt, np.float64) / d_t - np.asarray(ts, np.float64) / d_s)
+    b = len(r)
+    return float(math.fsum(r.tolist()) / b), (float(r.std(ddof=1) / math.sqrt(b)) if b > 1 else float("nan"))

@@ -52,6 +52,9 @@ def lib():
         L.oracle_absorbed.argtypes = [i64, P, P, i32, u64, u32, u64, i32, i64, i64, i64, i32,
                                       P, P, P, i64, P, i64, P, i32]
         L.oracle_absorbed.restype = i32
+        L.oracle_query_walks.argtypes = [i64, P, P, i32, u64, u32, u64, i32, i32, i32, i32, i64, i64,
+                                         P, P, P, P]
+        L.oracle_query_walks.restype = i32
         _lib = L
     return _lib
 
@@ -171,3 +174,16 @@ def absorbed(g, root, n_walks, seed, tag, *, stream=0, qid=0, walk_begin=0, omeg
                           n_walks, omega_total, B, _p(Y2), _p(ln), _p(sw), trace_walk,
                           _p(tr) if trace_cap else None, trace_cap, _p(tl), threads)
     return dict(Y2=Y2, len=ln, start=sw, trace=tr[: int(tl[0])] if trace_cap else None)
+
+
+def query_walks(g, root, seed, qid, start, sub, a, b, n_walks, *, stream=0, walk_begin=0):
+    """Walks from `start` absorbed at the root (sub-stream `sub`): departures
+    from a and from b, normalised length, length, per walk."""
+    n, rp, col = _graph(g)
+    da = np.zeros(n_walks, np.int64)
+    db = np.zeros(n_walks, np.int64)
+    nl = np.zeros(n_walks)
+    ln = np.zeros(n_walks, np.int64)
+    lib().oracle_query_walks(n, _p(rp), _p(col), int(root), seed, stream, qid, int(start), int(sub), int(a),
+                             int(b), walk_begin, n_walks, _p(da), _p(db), _p(nl), _p(ln))
+    return dict(dep_a=da, dep_b=db, norm_len=nl, len=ln)

@@ -338,3 +338,41 @@ int32_t oracle_absorbed(int64_t n, const int64_t *rp, const int32_t *col, int32_
     }
     return 0;
 }
+
+/* ------------------------------------------------------------ query walks */
+/*
+ * Walks for single-node and pairwise queries (Lemma 1, and the normalised
+ * path length lemma of Sec. 4.3).  Walk i (sub-stream sub = 0 from a, 1 from
+ * b) starts at its given node and moves to uniform neighbours until the root;
+ * its j-th move (j = 1, 2, ...) uses counter (i | 3<<56, j, sub, qid).  For
+ * every walk: the number of departures from a and from b, and the sum of
+ * 1/d_x over its departures x (accumulated in FP64 in walk order).
+ * Outputs [n_walks] each; NULL skips.
+ */
+int32_t oracle_query_walks(int64_t n, const int64_t *rp, const int32_t *col, int32_t root,
+                           uint64_t seed, uint32_t stream, uint64_t qid, int32_t start, int32_t sub,
+                           int32_t a, int32_t b, int64_t walk_begin, int64_t n_walks,
+                           int64_t *dep_a, int64_t *dep_b, double *norm_len, int64_t *len) {
+    (void)n;
+    uint64_t k0 = seed, k1 = make_key1(stream, root);
+    for (int64_t w = 0; w < n_walks; ++w) {
+        int64_t i = walk_begin + w;
+        int32_t u = start;
+        int64_t da = 0, db = 0, steps = 0;
+        double nl = 0.0;
+        while (u != root) {
+            int64_t d = rp[u + 1] - rp[u];
+            if (u == a) ++da;
+            if (u == b) ++db;
+            nl += 1.0 / (double)d;
+            ++steps;
+            uint64_t x = walk_draw(k0, k1, 3, (uint64_t)i, (uint64_t)steps, (uint64_t)sub, qid);
+            u = col[rp[u] + (int64_t)oracle_map_below(x, (uint64_t)d)];
+        }
+        if (dep_a) dep_a[w] = da;
+        if (dep_b) dep_b[w] = db;
+        if (norm_len) norm_len[w] = nl;
+        if (len) len[w] = steps;
+    }
+    return 0;
+}

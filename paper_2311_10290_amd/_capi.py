@@ -20,7 +20,11 @@ EXPORTS = [
     "lap_bench_gather",
     "lap_batch_create", "lap_batch_job_info", "lap_batch_run", "lap_batch_autotune", "lap_batch_result",
     "lap_batch_stats", "lap_batch_free",
+    "lap_server_create", "lap_server_submit", "lap_server_step", "lap_server_poll", "lap_server_pending",
+    "lap_server_globals", "lap_server_free",
 ]
+LAP_Q_CLOSENESS, LAP_Q_RESISTANCE, LAP_Q_KEMENY = 0, 1, 2
+LAP_SERVER_GLOBAL_QID = (1 << 64) - 1
 
 
 class SampleArgs(ctypes.Structure):
@@ -67,6 +71,24 @@ class BatchOut(ctypes.Structure):
                                                 "closeness", "trace", "kemeny", "kemeny_se")]
 
 
+class Query(ctypes.Structure):
+    _fields_ = [("qid", ctypes.c_int64), ("kind", ctypes.c_int32), ("u", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("budget", ctypes.c_int64)]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [("qid", ctypes.c_int64), ("kind", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("value", ctypes.c_double), ("se", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("root", ctypes.c_int32), ("stream", ctypes.c_uint32),
+                ("global_samples", ctypes.c_int64), ("arena_bytes", ctypes.c_int64), ("launches", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("items_per_launch", ctypes.c_int32), ("wilson_chunk", ctypes.c_int32),
+                ("timeout_s", ctypes.c_double)]
+
+
 def declare(lib):
     P, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
     sig = {
@@ -92,6 +114,13 @@ def declare(lib):
         "lap_batch_result": ([P, i32, ctypes.POINTER(BatchOut)], i32),
         "lap_batch_stats": ([P, P, P, P], i32),
         "lap_batch_free": ([P], None),
+        "lap_server_create": ([P, ctypes.POINTER(ServerConfig), P, P], i32),
+        "lap_server_submit": ([P, ctypes.POINTER(Query)], i32),
+        "lap_server_step": ([P, i32], i32),
+        "lap_server_poll": ([P, ctypes.POINTER(QueryResult), i32, P], i32),
+        "lap_server_pending": ([P, P, P, P], i32),
+        "lap_server_globals": ([P, P, P], i32),
+        "lap_server_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -252,6 +252,74 @@ class Batch:
         return dict(wilson_steps=v[0].value, absorbed_steps=v[1].value, trees=v[2].value)
 
 
+class Server:
+    """Request loop over a resident Graph (lap_server_*)."""
+
+    CLOSENESS, RESISTANCE, KEMENY = C.LAP_Q_CLOSENESS, C.LAP_Q_RESISTANCE, C.LAP_Q_KEMENY
+
+    def __init__(self, graph: "Graph", seed=1, root=-1, stream_id=0, global_samples=0, arena_bytes=0,
+                 launches=0, waves=0, items_per_launch=0, wilson_chunk=0, timeout_s=0.0, stream=None):
+        cfg = C.ServerConfig(seed=int(seed), root=int(root), stream=int(stream_id), global_samples=int(global_samples),
+                             arena_bytes=int(arena_bytes), launches=int(launches), waves=int(waves),
+                             items_per_launch=int(items_per_launch), wilson_chunk=int(wilson_chunk),
+                             timeout_s=float(timeout_s) if timeout_s else _default_timeout())
+        h = ctypes.c_void_p()
+        _check(load_library().lap_server_create(graph._h, ctypes.byref(cfg), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.graph = graph            # the graph must outlive the server
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().lap_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, qid, kind, budget, u=0, w=0):
+        _check(load_library().lap_server_submit(self._h, ctypes.byref(
+            C.Query(qid=int(qid), kind=int(kind), u=int(u), w=int(w), budget=int(budget)))))
+
+    def step(self, wait=False):
+        _check(load_library().lap_server_step(self._h, 1 if wait else 0))
+
+    def poll(self, max_results=4096):
+        buf = (C.QueryResult * max_results)()
+        k = ctypes.c_int32()
+        _check(load_library().lap_server_poll(self._h, buf, max_results, ctypes.byref(k)))
+        return [dict(qid=r.qid, kind=r.kind, status=r.status, value=r.value, se=r.se, t_submit=r.t_submit,
+                     t_start=r.t_start, t_done=r.t_done) for r in buf[: k.value]]
+
+    def pending(self):
+        v = [ctypes.c_int64() for _ in range(3)]
+        _check(load_library().lap_server_pending(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(queued=v[0].value, active=v[1].value, inflight=v[2].value)
+
+    def globals(self):
+        a = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(load_library().lap_server_globals(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def run_all(self, timeout_s=600.0):
+        """Drive the loop until every submitted query has completed."""
+        import time as _t
+        out = []
+        t0 = _t.time()
+        while True:
+            self.step(wait=True)
+            out += self.poll()
+            p = self.pending()
+            if p["queued"] == 0 and p["active"] == 0 and p["inflight"] == 0:
+                out += self.poll()
+                return out
+            if _t.time() - t0 > timeout_s:
+                raise TimeoutError("server did not drain")
+
+
 def bench_gather(bytes_, lanes, mode, stream=None):
     """Random 8-byte loads per second over a working set (mode 0 independent, 1 chase)."""
     r = ctypes.c_double()

@@ -18,33 +18,6 @@
 
 using namespace lap;
 
-// ------------------------------------------------------------------- handle
-struct lap_graph {
-    int device = 0;
-    int n_cu = 256;
-    double clock_khz = 100000.0;
-    HostCSR csr;
-    int32_t max_deg_node = 0, max_deg = 0;
-    DevBuf rp, nbr, col;
-    // sampling workspace
-    DevBuf state, epoch;
-    int64_t state_slots = 0;
-    bool state_dirty = false;
-    DevBuf y1, y2, y1s, len_u, len_p, keep_next, keep_draws, err, stats;
-    DevBuf asm_partial, asm_sums, asm_trace, est_out, blkcount;
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    int64_t last_stats[kNumStats] = {0};
-    ~lap_graph() {
-        DevBuf *bufs[] = {&rp, &nbr, &col, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
-                          &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount};
-        for (DevBuf *b : bufs) b->release();
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
-        if (aux) (void)hipStreamDestroy(aux);
-    }
-};
-
 extern "C" int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst,
                              uint32_t flags, void *hip_stream, lap_graph **out) {
     if (!out) return fail(LAP_EINVAL, "out is NULL");

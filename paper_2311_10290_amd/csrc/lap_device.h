@@ -181,4 +181,33 @@ struct BatchParams {
     uint64_t deadline;
 };
 
+// ------------------------------------------------------------ serving
+struct ServeItem {
+    int32_t kind;          // 0 Wilson samples, 2 stationary-start walks, 3 closeness walks, 4 resistance pairs
+    int32_t count;         // samples or walks in this item (<= 64 for walk items)
+    int64_t first;         // first sample / walk index within the query
+    int64_t budget;        // the query's sample / walk budget (stride of its result arrays)
+    int64_t qid;           // query id: Philox counter word 3
+    int32_t u, w;          // query nodes
+    int64_t out_off;       // the query's region in the result arena (8-byte words)
+};
+
+struct ServeParams {
+    int64_t n, nnz;
+    const uint64_t *nbr;
+    const int32_t *col;
+    int32_t root;
+    uint64_t k0, k1;
+    const ServeItem *items;
+    int64_t n_items;
+    unsigned long long *counter;
+    uint64_t *state;       // [slots][n]
+    uint32_t *slot_epoch;  // [slots]
+    int64_t slot_base;     // this launch's first slot
+    uint64_t *arena;       // result words
+    unsigned long long *stats;
+    DevErr *err;
+    uint64_t deadline;
+};
+
 }  // namespace lap

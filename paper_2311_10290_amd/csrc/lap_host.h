@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/lap.h"
+#include "lap_device.h"
 
 namespace lap {
 
@@ -59,3 +60,33 @@ struct DevBuf {
 };
 
 }  // namespace lap
+
+// The graph handle of include/lap.h: host CSR, device CSR and the sampling
+// workspace the calls reuse.
+struct lap_graph {
+    int device = 0;
+    int n_cu = 256;
+    double clock_khz = 100000.0;
+    lap::HostCSR csr;
+    int32_t max_deg_node = 0, max_deg = 0;
+    lap::DevBuf rp, nbr, col;
+    // sampling workspace
+    lap::DevBuf state, epoch;
+    int64_t state_slots = 0;
+    bool state_dirty = false;
+    lap::DevBuf y1, y2, y1s, len_u, len_p, keep_next, keep_draws, err, stats;
+    lap::DevBuf asm_partial, asm_sums, asm_trace, est_out, blkcount;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int64_t last_stats[lap::kNumStats] = {0};
+    ~lap_graph() {
+        lap::DevBuf *bufs[] = {&rp, &nbr, &col, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
+                          &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount};
+        for (lap::DevBuf *b : bufs) b->release();
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
+};
+
+

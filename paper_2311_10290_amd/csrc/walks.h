@@ -38,3 +38,38 @@ static __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag, int64_
 }
 
 }  // namespace lap
+
+namespace lap {
+
+// One query walk (Lemma 1; the normalised-length lemma of Sec. 4.3): from a
+// given start to the root, the j-th move using counter (i | 3<<56, j, sub,
+// qid).  Counts departures from a and from b and sums 1/d over departures in
+// walk order.  Returns false if the time limit passed (err is set).
+static __device__ bool query_walk(const WalkGraph &g, int32_t start, uint32_t sub, int64_t i, int32_t a, int32_t b,
+                                  int64_t *dep_a, int64_t *dep_b, double *norm_len, DevErr *err, uint64_t t0,
+                                  uint64_t deadline) {
+    const uint64_t c0 = (uint64_t)i | (3ull << 56);
+    int32_t u = start;
+    int64_t da = 0, db = 0, steps = 0;
+    double nl = 0.0;
+    while (u != g.root) {
+        const uint64_t nb = g.nbr[u];
+        const uint32_t d = nbr_deg(nb);
+        da += (u == a);
+        db += (u == b);
+        nl += 1.0 / (double)d;
+        ++steps;
+        const uint64_t x = philox_w0(c0, (uint64_t)steps, sub, g.qid, g.k0, g.k1);
+        u = g.col[nbr_off(nb) + (int64_t)pick_below(x, d)];
+        if ((steps & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
+            raise_err(err, kErrTimeout, 2);
+            return false;
+        }
+    }
+    *dep_a = da;
+    *dep_b = db;
+    *norm_len = nl;
+    return true;
+}
+
+}  // namespace lap
