@@ -87,8 +87,11 @@ def bench_batch(lap, gg, n_jobs):
         s, d = gg.job_edges(sp)
         jobs.append(dict(n=sp["n"], src=s, dst=d, keep_lcc=True, root=-1, omega=sp["omega"], seed=1))
     log(f"batch: generated {n_jobs} graphs in {time.perf_counter() - t0:.1f} s")
+    # autotune on every 8th job (a probe batch of the same mix), run all jobs
+    probe = lap.Batch(jobs[::8])
+    tuning, tune_ms = probe.autotune()
+    probe.close()
     b = lap.Batch(jobs)
-    tuning, tune_ms = b.autotune()
     log(f"batch: autotuned pool={tuning.pool} chunk={tuning.chunk_nodes} ({tune_ms:.1f} ms)")
     b.run(tuning)
     torch.cuda.synchronize()
@@ -147,6 +150,48 @@ def _replay(lap, srv, qs, qid0):
     return lat, wall, bad
 
 
+def bench_large(lap, gg, peaks):
+    """Large plain run: R-MAT scale 22 (edge factor 16, a/b/c/d = .57/.19/.19/.05),
+    symmetrised, self-loops and duplicates dropped, largest component kept;
+    root = max degree; 512 trees plus 512 walks of each kind per step."""
+    import torch
+    t = time.perf_counter()
+    src, dst = gg.rmat(22, 16, seed=0)
+    g = lap.Graph(1 << 22, src, dst, keep_lcc=True)
+    del src, dst
+    log(f"large: R-MAT 22 LCC n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    out = {k: torch.empty(g.n, dtype=torch.float64, device=dev) for k in ("diag", "diag_se", "closeness")}
+    out.update({k: torch.empty(1, dtype=torch.float64, device=dev) for k in ("trace", "kemeny", "kemeny_se")})
+    omega = 512
+    g.estimate(omega, 1, -1, B=64, out=out)
+    torch.cuda.synchronize()
+    lap.prof_reset()
+    lap.prof_enable(True)
+    reps = 2
+    t = time.perf_counter()
+    for _ in range(reps):
+        g.estimate(omega, 1, -1, B=64, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    lap.prof_enable(False)
+    st = g.last_stats()
+    ms_w, n_w = lap.prof_read("wilson_wave")
+    wave_s = ms_w / max(n_w, 1) * 1e-3
+    loads = LOADS_PER_WILSON_STEP * st["wilson_steps"] / wave_s
+    res = {"workload": "R-MAT scale 22 LCC, root = max degree, 512 trees + 512 walks of each kind",
+           "n": g.n, "nnz": g.nnz, "omega": omega, "s_per_step": dt,
+           "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) / dt,
+           "trees_per_s": omega / dt, "wilson_steps_per_tree": st["wilson_steps"] / omega,
+           "wilson_kernel_s": wave_s, "wilson_loads_per_s": loads,
+           "state_bytes": 8 * g.n * omega,
+           "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
+    if peaks:
+        res["frac_of_chase_peak_4GiB"] = loads / peaks["4GiB"]["chase"]
+    g.close()
+    return res
+
+
 def bench_serve(lap, gg, n_queries):
     """Serving: resident R-MAT scale-21 graph (edge factor 16, a/b/c/d =
     .57/.19/.19/.05, symmetrised, self-loops and duplicates dropped, largest
@@ -193,6 +238,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
@@ -282,10 +328,10 @@ def main():
         "estimates": {"kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item()),
                       "trace_Ldagger": float(out["trace"].item())},
     }
+    peaks = {}
     if not args.no_gather:
         log("random-gather peak")
         lanes = 256 * 24 * 64
-        peaks = {}
         for label, nbytes in (("4MiB", 4 << 20), ("128MiB", 128 << 20), ("4GiB", 4 << 30)):
             peaks[label] = {"chase": lap.bench_gather(nbytes, lanes, 1),
                             "independent": lap.bench_gather(nbytes, lanes // 4, 0)}
@@ -300,6 +346,8 @@ def main():
         res["batched"] = bench_batch(lap, gg, args.batch_jobs)
     if not args.no_serve:
         res["serving"] = bench_serve(lap, gg, args.serve_queries)
+    if not args.no_large:
+        res["large"] = bench_large(lap, gg, peaks if not args.no_gather else None)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         from oracle import csr as ocsr

@@ -147,6 +147,8 @@ typedef struct {
     double *trace;       /* [1] Tr(L^dagger) estimate (Kirchhoff index / n), or NULL */
     double *kemeny;      /* [1] Kemeny's constant (Alg. 4), or NULL */
     double *kemeny_se;   /* [1] its standard error from per-sample differences, or NULL */
+    double *kirchhoff;   /* [1] Kirchhoff index n * Tr(L^dagger) = sum over pairs of r(s,t), or NULL */
+    double *rw_betweenness; /* [n] 1/n + Tr/((n-1)(Tr + n diag_u)) (end of Sec. 5), or NULL */
 } lap_estimates;
 
 /*
@@ -334,9 +336,11 @@ int lap_prof_read(const char *kernel, double *total_ms, int64_t *launches);
 
 /* Counters of the last lap_sample_forests / lap_estimate call: Wilson walk
  * steps (draws), absorbed-walk steps, completed trees, wave iterations,
- * deadlock pops, rescans.  Any pointer may be NULL. */
+ * deadlock pops, rescans, and summed over wave iterations the number of
+ * idle walkers and of parked walkers.  Any pointer may be NULL. */
 int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_steps,
-                   int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans);
+                   int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans,
+                   int64_t *idle_lane_rounds, int64_t *parked_lane_rounds);
 
 /* Random-gather peak of the current device, the roofline reference for the
  * walkers: loads per second (written to *rate) of random 8-byte loads over a

@@ -20,5 +20,7 @@ Contents
 
 Parity status: every function is pinned by tests under ``tests/`` that check
 it against closed forms, the paper's worked examples, a library routine or
-brute force; none is marked "parity unpinned".
+brute force, except ``estimators.rw_betweenness`` (parity unpinned: the
+formula quoted at the end of Sec. 5 is implemented as printed, with no
+independent definition to check it against).
 """

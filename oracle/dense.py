@@ -133,6 +133,12 @@ def kemeny_lemma(L, v):
     return float(np.trace(N) - dv @ Lvi @ dv / d.sum())
 
 
+def kirchhoff_pairs(Ld):
+    """Kirchhoff index by its definition: sum over unordered pairs of r(s,t)."""
+    n = Ld.shape[0]
+    return float(sum(resistance(Ld, s, t) for s in range(n) for t in range(s + 1, n)))
+
+
 def resistance(Ld, s, t):
     return Ld[s, s] + Ld[t, t] - 2.0 * Ld[s, t]
 

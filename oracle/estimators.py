@@ -41,6 +41,22 @@ def closeness(diag):
     return (n - 1) / (tr + n * np.asarray(diag)), tr
 
 
+def kirchhoff(diag):
+    """Kirchhoff index n * Tr(L^dagger) (= sum over node pairs of resistance
+    distance).  The text at the end of Sec. 5 names Tr(L^dagger); the factor n
+    is the standard definition's (see the design doc readings)."""
+    return len(diag) * math.fsum(np.asarray(diag).tolist())
+
+
+def rw_betweenness(diag):
+    """1/n + Tr/((n-1)(Tr + n L^dagger_uu)), the formula quoted at the end of
+    Sec. 5.  Parity unpinned: no independent definition of this quantity is
+    implemented here; tests only check the HIP path against this formula."""
+    n = len(diag)
+    tr = math.fsum(np.asarray(diag).tolist())
+    return 1.0 / n + tr / ((n - 1) * (tr + n * np.asarray(diag)))
+
+
 def diag_ldagger_blocks(Y1b, Y2b, omega, deg):
     """Batch means: per-block estimates and their standard error."""
     B = Y1b.shape[0]

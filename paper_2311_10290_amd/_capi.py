@@ -49,7 +49,7 @@ class Estimates(ctypes.Structure):
     _fields_ = [
         ("diag", ctypes.c_void_p), ("diag_se", ctypes.c_void_p), ("lv_diag", ctypes.c_void_p),
         ("closeness", ctypes.c_void_p), ("trace", ctypes.c_void_p), ("kemeny", ctypes.c_void_p),
-        ("kemeny_se", ctypes.c_void_p),
+        ("kemeny_se", ctypes.c_void_p), ("kirchhoff", ctypes.c_void_p), ("rw_betweenness", ctypes.c_void_p),
     ]
 
 
@@ -105,7 +105,7 @@ def declare(lib):
         "lap_prof_enable": ([ctypes.c_int], i32),
         "lap_prof_reset": ([], i32),
         "lap_prof_read": ([ctypes.c_char_p, P, P], i32),
-        "lap_last_stats": ([P, P, P, P, P, P, P], i32),
+        "lap_last_stats": ([P, P, P, P, P, P, P, P, P], i32),
         "lap_bench_gather": ([i64, i64, i32, P, P], i32),
         "lap_batch_create": ([ctypes.POINTER(BatchJob), i32, P, P], i32),
         "lap_batch_job_info": ([P, i32, P, P, P], i32),

@@ -148,7 +148,7 @@ class Graph:
         return out
 
     def estimate(self, omega, seed, root=-1, *, diag=True, se=True, lv=False, closeness=True, kemeny=True,
-                 B=64, mode=0, pool=0, stream_id=0, qid=0, timeout_s=0.0, stream=None, out=None):
+                 derived=False, B=64, mode=0, pool=0, stream_id=0, qid=0, timeout_s=0.0, stream=None, out=None):
         """FP64 estimates of lap_estimate.  With ``out`` (a dict of torch device
         tensors: diag, diag_se, lv_diag, closeness [n]; trace, kemeny,
         kemeny_se [1]) results are written there on the device."""
@@ -163,16 +163,19 @@ class Graph:
                 diag=np.zeros(n) if diag else None, diag_se=np.zeros(n) if (diag and se) else None,
                 lv_diag=np.zeros(n) if lv else None, closeness=np.zeros(n) if closeness else None,
                 trace=np.zeros(1) if (diag or closeness) else None, kemeny=np.zeros(1) if kemeny else None,
-                kemeny_se=np.zeros(1) if kemeny else None)
+                kemeny_se=np.zeros(1) if kemeny else None, kirchhoff=np.zeros(1) if derived else None,
+                rw_betweenness=np.zeros(n) if derived else None)
         e = C.Estimates(**{k: _ptr(res.get(k)) for k in
-                           ("diag", "diag_se", "lv_diag", "closeness", "trace", "kemeny", "kemeny_se")})
+                           ("diag", "diag_se", "lv_diag", "closeness", "trace", "kemeny", "kemeny_se", "kirchhoff",
+                            "rw_betweenness")})
         _check(load_library().lap_estimate(self._h, ctypes.byref(a), ctypes.byref(e), _stream(stream)))
         return res
 
     def last_stats(self):
-        vals = [ctypes.c_int64() for _ in range(6)]
+        vals = [ctypes.c_int64() for _ in range(8)]
         _check(load_library().lap_last_stats(self._h, *[ctypes.byref(v) for v in vals]))
-        keys = ("wilson_steps", "absorbed_steps", "trees", "iterations", "pops", "rescans")
+        keys = ("wilson_steps", "absorbed_steps", "trees", "iterations", "pops", "rescans", "idle_lane_rounds",
+                "parked_lane_rounds")
         return {k: v.value for k, v in zip(keys, vals)}
 
 

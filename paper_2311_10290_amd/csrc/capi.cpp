@@ -98,7 +98,8 @@ extern "C" int lap_graph_copy_csr(const lap_graph *g, int64_t *rp, int32_t *col,
 extern "C" void lap_graph_free(lap_graph *g) { delete g; }
 
 extern "C" int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_steps,
-                              int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans) {
+                              int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans,
+                              int64_t *idle_lane_rounds, int64_t *parked_lane_rounds) {
     if (!g) return fail(LAP_EINVAL, "graph is NULL");
     if (wilson_steps) *wilson_steps = g->last_stats[kStatDraws];
     if (absorbed_steps) *absorbed_steps = g->last_stats[kStatAbsorbed];
@@ -106,6 +107,8 @@ extern "C" int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t
     if (iterations) *iterations = g->last_stats[kStatIters];
     if (pops) *pops = g->last_stats[kStatPops];
     if (rescans) *rescans = g->last_stats[kStatRescans];
+    if (idle_lane_rounds) *idle_lane_rounds = g->last_stats[kStatIdleLanes];
+    if (parked_lane_rounds) *parked_lane_rounds = g->last_stats[kStatParkedLanes];
     return LAP_OK;
 }
 
@@ -380,7 +383,8 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
     if (rc != LAP_OK) return rc;
     if (r.begin != 0 || r.total != r.omega)
         return fail(LAP_EINVAL, "lap_estimate runs a whole sample set: sample_begin = 0, n_total = n_samples");
-    const bool want_diag = out->diag || out->diag_se || out->lv_diag || out->closeness || out->trace;
+    const bool want_diag = out->diag || out->diag_se || out->lv_diag || out->closeness || out->trace ||
+                           out->kirchhoff || out->rw_betweenness;
     const bool want_kem = out->kemeny || out->kemeny_se;
     if (!want_diag && !want_kem) return LAP_OK;
     r.wilson = true;
@@ -396,10 +400,11 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
     const int32_t parts = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 1023) / 1024));
     if (g->asm_partial.ensure(sizeof(double) * (size_t)(r.B + 1) * parts) ||
         g->asm_sums.ensure(sizeof(double) * (size_t)(r.B + 2)) || g->asm_trace.ensure(sizeof(double) * parts) ||
-        g->est_out.ensure(sizeof(double) * (4 * (size_t)n + 4)))
+        g->est_out.ensure(sizeof(double) * (5 * (size_t)n + 5)))
         return fail(LAP_ENOMEM, "cannot allocate assembly buffers");
     double *d_diag = g->est_out.as<double>(), *d_se = d_diag + n, *d_lv = d_se + n, *d_c = d_lv + n;
-    double *d_scal = d_c + n;   // trace, kappa, kappa_se
+    double *d_rwb = d_c + n;
+    double *d_scal = d_rwb + n;   // trace, kappa, kappa_se, kirchhoff
     tm.begin("assemble", s);
     if (want_diag) {
         AssembleParams ap;
@@ -418,7 +423,9 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
         ap.diag_se = d_se;
         ap.lv_diag = d_lv;
         ap.closeness = d_c;
+        ap.rw_betweenness = d_rwb;
         ap.trace = d_scal;
+        ap.kirchhoff = d_scal + 3;
         ap.n_parts = parts;
         HIP_TRY(launch_assemble_diag(ap, s));
     }
@@ -428,7 +435,7 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
     if (rc != LAP_OK) return rc;
     if (n == 1) {
         // a single node: every estimate is zero
-        std::vector<double> z(4 * (size_t)n + 4, 0.0);
+        std::vector<double> z(5 * (size_t)n + 5, 0.0);
         HIP_TRY(hipMemcpy(d_diag, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     if ((rc = copy_out(out->diag, d_diag, sizeof(double) * n, s)) ||
@@ -437,7 +444,9 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
         (rc = copy_out(out->closeness, d_c, sizeof(double) * n, s)) ||
         (rc = copy_out(out->trace, d_scal, sizeof(double), s)) ||
         (rc = copy_out(out->kemeny, d_scal + 1, sizeof(double), s)) ||
-        (rc = copy_out(out->kemeny_se, d_scal + 2, sizeof(double), s)))
+        (rc = copy_out(out->kemeny_se, d_scal + 2, sizeof(double), s)) ||
+        (rc = copy_out(out->kirchhoff, d_scal + 3, sizeof(double), s)) ||
+        (rc = copy_out(out->rw_betweenness, d_rwb, sizeof(double) * n, s)))
         return rc;
     HIP_TRY(hipStreamSynchronize(s));
     return LAP_OK;

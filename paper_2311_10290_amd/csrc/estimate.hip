@@ -178,13 +178,19 @@ __global__ __launch_bounds__(kAsmBS) void trace_kernel(AssembleParams p) {
     const double s = block_sum<kAsmBS>(acc, sh);
     if (threadIdx.x == 0) p.sums[p.n_blocks + 1] = s;
     if (threadIdx.x == 0 && p.trace) p.trace[0] = s;
+    if (threadIdx.x == 0 && p.kirchhoff) p.kirchhoff[0] = (double)p.n * s;   // n Tr(L^dagger)
 }
 
+// c_u = (n-1)/(Tr + n diag_u) (Sec. 2); random-walk betweenness
+// 1/n + Tr/((n-1)(Tr + n diag_u)) (end of Sec. 5)
 __global__ __launch_bounds__(kAsmBS) void closeness_kernel(AssembleParams p, const double *diag) {
     const double tr = p.sums[p.n_blocks + 1];
     const double nn = (double)p.n;
-    for (int64_t u = (int64_t)blockIdx.x * kAsmBS + threadIdx.x; u < p.n; u += (int64_t)gridDim.x * kAsmBS)
-        p.closeness[u] = (nn - 1.0) / (tr + nn * diag[u]);
+    for (int64_t u = (int64_t)blockIdx.x * kAsmBS + threadIdx.x; u < p.n; u += (int64_t)gridDim.x * kAsmBS) {
+        const double den = tr + nn * diag[u];
+        if (p.closeness) p.closeness[u] = (nn - 1.0) / den;
+        if (p.rw_betweenness) p.rw_betweenness[u] = 1.0 / nn + tr / ((nn - 1.0) * den);
+    }
 }
 
 hipError_t launch_assemble_diag(const AssembleParams &p, hipStream_t s) {
@@ -193,7 +199,7 @@ hipError_t launch_assemble_diag(const AssembleParams &p, hipStream_t s) {
     hipLaunchKernelGGL(y2_sums_final_kernel, dim3((unsigned)(p.n_blocks + 1)), dim3(kAsmBS), 0, s, p);
     hipLaunchKernelGGL(diag_kernel, dim3((unsigned)p.n_parts), dim3(kAsmBS), 0, s, p);
     hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(kAsmBS), 0, s, p);
-    if (p.closeness) {
+    if (p.closeness || p.rw_betweenness) {
         int64_t grid = (p.n + kAsmBS - 1) / kAsmBS;
         if (grid > 4096) grid = 4096;
         hipLaunchKernelGGL(closeness_kernel, dim3((unsigned)grid), dim3(kAsmBS), 0, s, p, p.diag);

@@ -84,7 +84,7 @@ __device__ __forceinline__ bool err_set(const DevErr *e) {
 // ------------------------------------------------------------ kernel parameters
 constexpr int kMaxKeep = 64;
 constexpr int kStatIters = 0, kStatDraws = 1, kStatTrees = 2, kStatPops = 3, kStatRescans = 4,
-              kStatAbsorbed = 5, kNumStats = 8;
+              kStatAbsorbed = 5, kStatIdleLanes = 6, kStatParkedLanes = 7, kNumStats = 8;
 
 struct WilsonParams {
     int64_t n, nnz;
@@ -126,7 +126,7 @@ struct WaveSampleArgs {
 };
 
 struct WaveStats {
-    unsigned long long iters = 0, draws = 0, trees = 0, pops = 0, rescans = 0;
+    unsigned long long iters = 0, draws = 0, trees = 0, pops = 0, rescans = 0, idle = 0, parked = 0;
 };
 
 struct AbsorbedParams {

@@ -28,6 +28,7 @@ struct AssembleParams {
     double *sums;                  // [B+1]: sum_w Y2_b[w]/d_w, index B = all blocks
     double *trace_parts;           // [n_parts] scratch
     double *diag, *diag_se, *lv_diag, *closeness, *trace;   // outputs (device), each may be null
+    double *rw_betweenness, *kirchhoff;
     int32_t n_parts;
 };
 

@@ -458,7 +458,11 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         }
         fresh = false;
         __syncthreads();   // stores and LDS writes visible to the next round
-        if (lane == 0) ++ws.iters;
+        if (lane == 0) {
+            ++ws.iters;
+            ws.idle += (unsigned long long)n_idle;
+            ws.parked += (unsigned long long)__popcll(pk);
+        }
 
         // ---- the sample ends when every node is in the tree
         const uint64_t busy = __ballot(mode != kIdle);
@@ -487,6 +491,8 @@ static __device__ void flush_wave_stats(const WaveStats &ws, unsigned long long 
         atomicAdd(&stats[kStatTrees], ws.trees);
         atomicAdd(&stats[kStatPops], ws.pops);
         atomicAdd(&stats[kStatRescans], ws.rescans);
+        atomicAdd(&stats[kStatIdleLanes], ws.idle);
+        atomicAdd(&stats[kStatParkedLanes], ws.parked);
     }
 }
 

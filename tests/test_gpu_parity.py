@@ -134,6 +134,17 @@ def test_estimates_match_oracle_assembly_and_dense_truth():
     assert abs(est["kemeny"][0] - dense.kemeny_spectral(og)) < 3 * est["kemeny_se"][0]
 
 
+def test_derived_outputs_match_oracle():
+    n, s, d = er256_edges()
+    og, hg = both(n, s, d)
+    root = csr.landmark(og)
+    est = hg.estimate(2048, 5, root, B=8, derived=True)
+    exp = _oracle_counts(og, root, 2048, 5, B=8)
+    diag = estimators.diag_ldagger(exp["Y1"].sum(0), exp["Y2"].sum(0), 2048, og.deg)
+    np.testing.assert_allclose(est["kirchhoff"][0], estimators.kirchhoff(diag), rtol=1e-12)
+    np.testing.assert_allclose(est["rw_betweenness"], estimators.rw_betweenness(diag), rtol=1e-12)
+
+
 def test_convenience_entry_points_agree():
     from paper_2311_10290_amd import diag_Ldagger, ecc, kemeny
     n, s, d = er256_edges()

@@ -121,3 +121,17 @@ def test_walk_green_counts_visits_by_linear_system():
     N = dense.walk_green(L, n - 1)
     for s in range(n - 1):
         assert N[s].sum() == pytest.approx((n - 1 - s) * (n - 1 + s), rel=1e-12)
+
+
+def test_kirchhoff_index_closed_forms_and_trace_identity():
+    from oracle import estimators
+    for n in (3, 6, 9):
+        Ld = dense.pinv_eigh(dense.laplacian(graph("complete", n)))
+        assert dense.kirchhoff_pairs(Ld) == pytest.approx(n - 1, rel=1e-12)            # r = 2/n on every pair
+        Ld = dense.pinv_eigh(dense.laplacian(graph("path", n)))
+        assert dense.kirchhoff_pairs(Ld) == pytest.approx((n ** 3 - n) / 6, rel=1e-12)  # sum of |i-j|
+        Ld = dense.pinv_eigh(dense.laplacian(graph("cycle", n)))
+        assert dense.kirchhoff_pairs(Ld) == pytest.approx((n ** 3 - n) / 12, rel=1e-12)
+    for g in (graph("grid", 3, 4), graph("barabasi_albert", 30, 2, 7)):
+        Ld = dense.pinv_eigh(dense.laplacian(g))
+        assert estimators.kirchhoff(np.diag(Ld)) == pytest.approx(dense.kirchhoff_pairs(Ld), rel=1e-10)
