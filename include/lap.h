@@ -261,7 +261,9 @@ void lap_batch_free(lap_batch *b);
  * result regions fit in the device result arena (arena_bytes), and starts a
  * launch on every idle stream with the active queries' next work items, one
  * per query per round (continuous batching: queries that arrive while
- * launches are running join the next launch).  Completed queries are
+ * launches are running join the next launch).  With two or more streams,
+ * even-numbered streams carry walk tiles and odd ones Wilson samples, so
+ * short queries do not wait behind the Wilson samples of Kemeny queries.  Completed queries are
  * assembled on the host in FP64 and returned by lap_server_poll.
  */
 typedef struct lap_server lap_server;

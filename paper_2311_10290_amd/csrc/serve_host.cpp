@@ -222,8 +222,9 @@ int retire(lap_server *s, SLaunch &L) {
     return LAP_OK;
 }
 
-// next work item of a query, or false if all have been issued
-bool next_item(lap_server *s, SQuery &Q, ServeItem &it) {
+// next work item of a query for a launch of class cls (0: walk tiles, 1:
+// Wilson samples, 2: either), or false if it has none left of that class
+bool next_item(lap_server *s, SQuery &Q, ServeItem &it, int cls) {
     const int64_t b = Q.q.budget;
     std::memset(&it, 0, sizeof it);
     it.budget = b;
@@ -232,8 +233,8 @@ bool next_item(lap_server *s, SQuery &Q, ServeItem &it) {
     it.w = Q.q.w;
     it.out_off = Q.off;
     if (Q.q.kind == LAP_Q_KEMENY) {
-        // alternate Wilson chunks and walk tiles
-        const bool wil_left = Q.next_wilson < b, pi_left = Q.next_pi < b;
+        const bool wil_left = Q.next_wilson < b && cls != 0;
+        const bool pi_left = Q.next_pi < b && cls != 1;
         if (!wil_left && !pi_left) return false;
         if (wil_left && (!pi_left || Q.issued % 2 == 0)) {
             it.kind = 0;
@@ -247,7 +248,7 @@ bool next_item(lap_server *s, SQuery &Q, ServeItem &it) {
             Q.next_pi += it.count;
         }
     } else {
-        if (Q.next_walk >= b) return false;
+        if (cls == 1 || Q.next_walk >= b) return false;
         it.kind = Q.q.kind == LAP_Q_CLOSENESS ? 3 : 4;
         it.first = Q.next_walk;
         it.count = (int32_t)std::min<int64_t>(64, b - Q.next_walk);
@@ -257,8 +258,12 @@ bool next_item(lap_server *s, SQuery &Q, ServeItem &it) {
     return true;
 }
 
+// With two or more launches, even-numbered streams run walk tiles and odd
+// ones Wilson samples, so short walk queries never wait for a Wilson sample
+// of a Kemeny query that shares their launch.
 int launch(lap_server *s, int idx) {
     SLaunch &L = s->launches[idx];
+    const int cls = s->launches.size() < 2 ? 2 : (idx % 2);
     int64_t cnt = 0;
     bool any = true;
     const double t = now_s(s->t0);
@@ -268,7 +273,7 @@ int launch(lap_server *s, int idx) {
             SQuery &Q = kv.second;
             if (cnt >= s->cfg.items_per_launch) break;
             if (Q.issued >= Q.n_items) continue;
-            if (next_item(s, Q, L.h_items[cnt])) {
+            if (next_item(s, Q, L.h_items[cnt], cls)) {
                 L.serials.push_back(kv.first);
                 if (Q.t_start < 0) Q.t_start = t;
                 ++cnt;

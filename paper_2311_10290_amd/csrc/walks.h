@@ -17,7 +17,7 @@ struct WalkGraph {
 };
 
 // Returns the walk's length, or -1 if the time limit passed (p.err is set).
-static __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag, int64_t i, unsigned long long *y2,
+static inline __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag, int64_t i, unsigned long long *y2,
                                         DevErr *err, uint64_t t0, uint64_t deadline) {
     const uint64_t c0 = (uint64_t)i | ((uint64_t)tag << 56);
     const uint64_t x0 = philox_w0(c0, 0, 0, g.qid, g.k0, g.k1);
@@ -45,7 +45,7 @@ namespace lap {
 // given start to the root, the j-th move using counter (i | 3<<56, j, sub,
 // qid).  Counts departures from a and from b and sums 1/d over departures in
 // walk order.  Returns false if the time limit passed (err is set).
-static __device__ bool query_walk(const WalkGraph &g, int32_t start, uint32_t sub, int64_t i, int32_t a, int32_t b,
+static inline __device__ bool query_walk(const WalkGraph &g, int32_t start, uint32_t sub, int64_t i, int32_t a, int32_t b,
                                   int64_t *dep_a, int64_t *dep_b, double *norm_len, DevErr *err, uint64_t t0,
                                   uint64_t deadline) {
     const uint64_t c0 = (uint64_t)i | (3ull << 56);

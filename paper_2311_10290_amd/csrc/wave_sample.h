@@ -48,15 +48,32 @@ struct WaveShared {
     uint8_t stk_k[kStackDepth][kWave];
     uint8_t claim_tbl[1 << kClaimBits];
     int32_t rev[kRevCap];
-    int32_t cand[kScanChunks * kWave];
+    int32_t cand_node[kWave];
+    uint64_t cand_st[kWave];
+    uint64_t cand_nb[kWave];
     int32_t ent[kWave];
     int32_t mark[kWave];
     int64_t cut_at;
 };
 
+// LDS ordering inside the single-wave workgroup: wait for this wave's LDS
+// operations, no wait on global memory
+static __device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One Wilson sample run by the calling wavefront.  Returns false when the
 // sample was abandoned (error or time limit; c.err says which); *y1_out is
 // the sample's total number of draws.
+//
+// A round of the loop: (1) the drawing walkers load their drawn column entry
+// (read-only data); (2) a workgroup fence makes the previous round's state
+// stores visible -- their completion overlaps the column loads; (3) every
+// arriving walker loads its target's state word and adjacency record, and
+// the scan loads the next candidate starts; (4) walkers act on what they
+// loaded; walkers that are idle now take free candidates from this round's
+// scan and claim them at once.
 static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &sh, int64_t *y1_out, WaveStats &ws) {
     const int lane = (int)threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -70,7 +87,6 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         if (c.keep_next) c.keep_next[c.root] = -1;
         if (c.keep_draws) c.keep_draws[c.root] = 0;
     }
-    __syncthreads();
 
     int64_t cursor = 0;        // next node id the scan looks at (wave-uniform)
     int rev_n = 0;             // entries in rev[] (wave-uniform)
@@ -89,14 +105,29 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
 
     // write the stack out as path words: entry j points to entry j+1, the top
     // to top_next (memory mode from here on)
-    auto flush_stack = [&](int32_t top_next) {
+    auto flush_stack = [&](int32_t top_next, uint32_t top_k) {
         for (int j = 0; j < depth; ++j) {
             const int32_t node = sh.stk_node[j][lane];
-            const int32_t nx = (j + 1 < depth) ? sh.stk_node[j + 1][lane] : top_next;
-            st[node] = st_pack(nx, sh.stk_k[j][lane], me, ep);
+            const bool top = j + 1 == depth;
+            const int32_t nx = top ? top_next : sh.stk_node[j + 1][lane];
+            st[node] = st_pack(nx, top ? top_k : (uint32_t)sh.stk_k[j][lane], me, ep);
         }
         depth = 0;
         mem = true;
+    };
+    auto push_round = [&](bool pu, int32_t node) {
+        const uint64_t pm = __ballot(pu);
+        if (pm) {
+            const int r = __popcll(pm & below);
+            const int cnt = __popcll(pm);
+            if (pu && rev_n + r < kRevCap) sh.rev[rev_n + r] = node;
+            if (rev_n + cnt > kRevCap) {
+                overflow = true;
+                rev_n = kRevCap;
+            } else {
+                rev_n += cnt;
+            }
+        }
     };
 
     while (true) {
@@ -109,10 +140,33 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                 return false;
             }
         }
+        // ---- R1. read-only loads: drawn column entries, resumed heads' adjacency
+        int64_t la_col = -1, la_nb1 = -1;
+        if (mode == kDraw) {
+            const uint64_t r = philox_w0((uint64_t)sample, (uint64_t)h, kh, c.qid, c.k0, c.k1);
+            la_col = nbr_off(nbh) + (int64_t)pick_below(r, nbr_deg(nbh));
+        } else if (mode == kNbLoad) {
+            la_nb1 = h;
+        }
+        {
+            // every index must stay inside the graph; anything else is a bug
+            // and stops the kernel instead of touching memory out of bounds
+            const bool oob = (mode == kDraw && (h < 0 || h >= n || la_col < 0 || la_col >= c.nnz)) ||
+                             (mode == kNbLoad && (la_nb1 < 0 || la_nb1 >= n));
+            if (__ballot(oob)) {
+                if (oob) raise_err(c.err, kErrInconsistent, -1);
+                return false;
+            }
+        }
+        const int32_t a_col = (la_col >= 0) ? c.col[la_col] : 0;
+        const uint64_t a_nb1 = (la_nb1 >= 0) ? c.nbr[la_nb1] : 0ull;
+
+        // ---- fence: the previous round's stores and LDS writes are visible
+        __syncthreads();
+
         // ---- 1. idle walkers take released nodes the scan has passed
         const uint64_t idle = __ballot(mode == kIdle);
         const int n_idle = __popcll(idle);
-        bool scanning = false;
         if (n_idle > 0) {
             const int take = min(n_idle, rev_n);
             if (mode == kIdle) {
@@ -124,41 +178,6 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                 }
             }
             rev_n -= take;
-            scanning = (n_idle > take) && (cursor < n);
-        }
-
-        // ---- A. first round of loads: draws, memory-mode walks, the scan
-        int64_t la_st = -1, la_nb = -1, la_col = -1;
-        if (mode == kDraw) {
-            const uint64_t r = philox_w0((uint64_t)sample, (uint64_t)h, kh, c.qid, c.k0, c.k1);
-            la_col = nbr_off(nbh) + (int64_t)pick_below(r, nbr_deg(nbh));
-        } else if (mode == kRetrace || mode == kRelease) {
-            la_st = x;
-        } else if (mode == kPopLoad) {
-            la_st = e;
-            la_nb = e;
-        } else if (mode == kNbLoad) {
-            la_nb = h;
-        }
-        {
-            // every index must stay inside the graph; anything else is a bug
-            // and stops the kernel instead of touching memory out of bounds
-            const bool oob = ((mode == kRetrace || mode == kRelease || mode == kPopLoad) && (la_st < 0 || la_st >= n)) ||
-                             ((mode == kPopLoad || mode == kNbLoad) && (la_nb < 0 || la_nb >= n)) ||
-                             (mode == kDraw && (h < 0 || h >= n || la_col < 0 || la_col >= c.nnz));
-            if (__ballot(oob)) {
-                if (oob) raise_err(c.err, kErrInconsistent, -1);
-                return false;
-            }
-        }
-        const uint64_t a_st = (la_st >= 0) ? st[la_st] : 0ull;
-        const uint64_t a_nb = (la_nb >= 0) ? c.nbr[la_nb] : 0ull;
-        const int32_t a_col = (la_col >= 0) ? c.col[la_col] : 0;
-        uint64_t v_scan[kScanChunks];
-#pragma unroll
-        for (int q = 0; q < kScanChunks; ++q) {
-            const int64_t sc = cursor + q * kWave + lane;
-            v_scan[q] = (scanning && sc < n) ? st[sc] : 0ull;
         }
 
         // ---- 2. finish draws: the drawn neighbour becomes the next target
@@ -172,14 +191,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                 st[h] = st_pack(w, kh + 1, me, ep);
                 kh += 1;
             } else if (kh + 1 > kStackMaxK) {
-                for (int j = 0; j < depth; ++j) {
-                    const int32_t node = sh.stk_node[j][lane];
-                    const int32_t nx = (j + 1 < depth) ? sh.stk_node[j + 1][lane] : w;
-                    const uint32_t kk = (j + 1 < depth) ? sh.stk_k[j][lane] : kh + 1;
-                    st[node] = st_pack(nx, kk, me, ep);
-                }
-                depth = 0;
-                mem = true;
+                flush_stack(w, kh + 1);
                 kh += 1;
                 fresh = true;      // arrive next round, once the words are visible
             } else {
@@ -190,54 +202,40 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
             mode = kArrive;
             is_start = false;
         } else if (mode == kNbLoad) {
-            nbh = a_nb;
+            nbh = a_nb1;
             mode = kDraw;
         }
 
-        // ---- 3. scan: hand FREE candidates to the remaining idle walkers
-        if (scanning) {
-            uint64_t m[kScanChunks];
-            int nf = 0;
-#pragma unroll
-            for (int q = 0; q < kScanChunks; ++q) {
-                const int64_t sc = cursor + q * kWave + lane;
-                m[q] = __ballot(sc < n && st_tag(v_scan[q], ep) == kTagFree);
-                nf += __popcll(m[q]);
-            }
-            const uint64_t idle2 = __ballot(mode == kIdle);
-            const int need = __popcll(idle2);
-            int base = 0;
-#pragma unroll
-            for (int q = 0; q < kScanChunks; ++q) {
-                const bool f = (m[q] >> lane) & 1ull;
-                const int qq = base + __popcll(m[q] & below);
-                const int64_t sc = cursor + q * kWave + lane;
-                if (f && qq < need) sh.cand[qq] = (int32_t)sc;
-                if (f && qq == need - 1 && nf > need) sh.cut_at = sc + 1;
-                base += __popcll(m[q]);
-            }
-            __syncthreads();
-            const int got = min(need, nf);
-            if (mode == kIdle) {
-                const int r = __popcll(idle2 & below);
-                if (r < got) {
-                    w = sh.cand[r];
-                    mode = kArrive;
-                    is_start = true;
-                }
-            }
-            cursor = (nf > need) ? sh.cut_at : min(n, cursor + kScanChunks * kWave);
-        }
-
-        // ---- B. second round of loads: every arriving walker's target
+        // ---- R2. state loads: arriving walkers, memory-mode walkers, the scan
         const bool arriving = (mode == kArrive) && !fresh;
-        if (arriving && (w < 0 || w >= n)) bad = true;
+        int64_t lb_st = -1, lb_nb = -1;
+        if (arriving) {
+            lb_st = w;
+            lb_nb = w;
+        } else if (mode == kRetrace || mode == kRelease) {
+            lb_st = x;
+        } else if (mode == kPopLoad) {
+            lb_st = e;
+            lb_nb = e;
+        }
+        if ((lb_st >= 0 && lb_st >= n) || (lb_nb >= 0 && lb_nb >= n) ||
+            ((arriving || mode == kRetrace || mode == kRelease || mode == kPopLoad) && lb_st < 0))
+            bad = true;
         if (__ballot(bad)) {
             if (bad) raise_err(c.err, kErrInconsistent, -2);
             return false;
         }
-        const uint64_t v_st = arriving ? st[w] : a_st;
-        const uint64_t v_nb = arriving ? c.nbr[w] : a_nb;
+        const int scan_chunks = (cursor < n) ? (n_idle > 0 ? kScanChunks : 1) : 0;   // wave-uniform
+        uint64_t v_st = (lb_st >= 0) ? st[lb_st] : 0ull;
+        uint64_t v_nb = (lb_nb >= 0) ? c.nbr[lb_nb] : 0ull;
+        uint64_t sc_st[kScanChunks], sc_nb[kScanChunks];
+#pragma unroll
+        for (int q = 0; q < kScanChunks; ++q) {
+            const int64_t sc = cursor + q * kWave + lane;
+            const bool ld = q < scan_chunks && sc < n;
+            sc_st[q] = ld ? st[sc] : 0ull;
+            sc_nb[q] = ld ? c.nbr[sc] : 0ull;
+        }
 
         // ---- C. advance every walker by what its loads returned
         bool claim = false, parked = false, push = false;
@@ -322,10 +320,8 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         } else if (mode == kRelease) {
             const int32_t nx = st_next(v_st);
             st[x] = st_pack(nx, st_k(v_st, ep), kTagFree, ep);
-            if (x < cursor) {
-                push = true;
-                pushed = x;
-            }
+            push = true;
+            pushed = x;
             if (x == stop_at) {
                 h = e;
                 kh = ke;
@@ -346,9 +342,53 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
             return false;
         }
 
+        // ---- scan: walkers idle now take FREE candidates and claim them
+        if (scan_chunks > 0) {
+            const uint64_t idle2 = __ballot(mode == kIdle);
+            const int need = __popcll(idle2);
+            if (need > 0) {
+                uint64_t m[kScanChunks];
+                int nf = 0;
+#pragma unroll
+                for (int q = 0; q < kScanChunks; ++q) {
+                    const int64_t sc = cursor + q * kWave + lane;
+                    m[q] = __ballot(q < scan_chunks && sc < n && st_tag(sc_st[q], ep) == kTagFree);
+                    nf += __popcll(m[q]);
+                }
+                int base = 0;
+#pragma unroll
+                for (int q = 0; q < kScanChunks; ++q) {
+                    const bool f = (m[q] >> lane) & 1ull;
+                    const int qq = base + __popcll(m[q] & below);
+                    const int64_t sc = cursor + q * kWave + lane;
+                    if (f && qq < need) {
+                        sh.cand_node[qq] = (int32_t)sc;
+                        sh.cand_st[qq] = sc_st[q];
+                        sh.cand_nb[qq] = sc_nb[q];
+                    }
+                    if (f && qq == need - 1 && nf > need) sh.cut_at = sc + 1;
+                    base += __popcll(m[q]);
+                }
+                wave_lds_sync();
+                const int got = min(need, nf);
+                if (mode == kIdle) {
+                    const int r = __popcll(idle2 & below);
+                    if (r < got) {
+                        w = sh.cand_node[r];
+                        v_st = sh.cand_st[r];
+                        v_nb = sh.cand_nb[r];
+                        mode = kArrive;
+                        is_start = true;
+                        claim = true;
+                    }
+                }
+                cursor = (nf > need) ? sh.cut_at : min(n, cursor + (int64_t)scan_chunks * kWave);
+            }
+        }
+
         // ---- claims of free nodes, deduplicated through an LDS table
         if (claim) sh.claim_tbl[w & kClaimMask] = (uint8_t)lane;
-        __syncthreads();
+        wave_lds_sync();
         const int winner = claim ? (int)sh.claim_tbl[w & kClaimMask] : lane;
         const int32_t w_win = __shfl(w, winner, kWave);
         if (claim) {
@@ -360,7 +400,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                     mem = false;
                     depth = 0;
                 }
-                if (!mem && (depth == kStackDepth || kw > kStackMaxK)) flush_stack(w);
+                if (!mem && (depth == kStackDepth || kw > kStackMaxK)) flush_stack(w, (uint32_t)sh.stk_k[depth > 0 ? depth - 1 : 0][lane]);
                 st[w] = st_pack(-1, kw, me, ep);
                 if (!mem) {
                     sh.stk_node[depth][lane] = w;
@@ -380,6 +420,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                 }
             }
             // otherwise a different node hashed to the same slot: retry
+            // (a start candidate that lost this way is looked at again next round)
         }
 
         // ---- rings of parked walkers are cycles of stack tops: pop them
@@ -390,12 +431,12 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
 #pragma unroll
             for (int r = 0; r < 6; ++r) g = __shfl(g, g, kWave);   // g = f^64(lane)
             sh.mark[lane] = 0;
-            __syncthreads();
+            wave_lds_sync();
             sh.mark[g] = 1;
-            __syncthreads();
+            wave_lds_sync();
             const bool on_cycle = parked && sh.mark[lane] != 0;
             if (on_cycle) sh.ent[f] = w;
-            __syncthreads();
+            wave_lds_sync();
             if (on_cycle) {
                 e = sh.ent[lane];
                 parked = false;
@@ -430,21 +471,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         }
 
         // ---- released nodes: free words; those behind the scan go on the revisit list
-        auto push_round = [&](bool pu, int32_t node) {
-            const uint64_t pm = __ballot(pu);
-            if (pm) {
-                const int r = __popcll(pm & below);
-                const int cnt = __popcll(pm);
-                if (pu && rev_n + r < kRevCap) sh.rev[rev_n + r] = node;
-                if (rev_n + cnt > kRevCap) {
-                    overflow = true;
-                    rev_n = kRevCap;
-                } else {
-                    rev_n += cnt;
-                }
-            }
-        };
-        push_round(push, pushed);
+        push_round(push && pushed < cursor, pushed);
         if (__ballot(rel_hi > rel_lo)) {
             for (int j = 0; j < kStackDepth; ++j) {
                 const bool act = j >= rel_lo && j < rel_hi;
@@ -457,7 +484,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
             }
         }
         fresh = false;
-        __syncthreads();   // stores and LDS writes visible to the next round
+        wave_lds_sync();
         if (lane == 0) {
             ++ws.iters;
             ws.idle += (unsigned long long)n_idle;
@@ -479,6 +506,8 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
             }
         }
     }
+    // leave the sample's stores visible before the slot is reused
+    __syncthreads();
     *y1_out = wave_sum_i64(y1_local);
     return true;
 }
