@@ -113,6 +113,8 @@ typedef struct {
     int32_t mode;          /* LAP_MODE_* */
     int32_t pool;          /* concurrent samples (slots); 0 = automatic */
     double timeout_s;      /* kernel time limit; 0 = 120 s */
+    int64_t schedule;      /* wave form: the start scan begins at node (schedule mod n) and wraps;
+                              counts do not depend on it (a knob for schedule-randomised tests) */
 } lap_sample_args;
 
 typedef struct {
@@ -235,6 +237,18 @@ int lap_batch_result(const lap_batch *b, int32_t job, lap_batch_out *out);
 /* Walk steps and trees of the last run, all jobs together. */
 int lap_batch_stats(const lap_batch *b, int64_t *wilson_steps, int64_t *absorbed_steps, int64_t *trees);
 void lap_batch_free(lap_batch *b);
+
+/*
+ * lap_landmark_traces -- the landmark study (Sec. 6.2, the effect of the
+ * landmark; Table 1 reports Tr((I-P_v)^{-1})/n): for each roots[j], omega
+ * Wilson samples rooted there (seed, stream 0, qid 0: the same draws as
+ * lap_sample_forests with that root); trace[j] receives their mean total
+ * draws, an unbiased estimate of Tr((I-P_v)^{-1}) -- the expected cost of
+ * one sample (Sec. 3.3) -- and trace_se[j] (may be NULL) its standard error.
+ * All roots run in one persistent launch over the shared graph.
+ */
+int lap_landmark_traces(lap_graph *g, const int32_t *roots, int32_t n_roots, int64_t omega, uint64_t seed,
+                        double *trace, double *trace_se, void *hip_stream);
 
 /* ---------------------------------------------------------------- serving */
 

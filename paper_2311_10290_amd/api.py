@@ -115,20 +115,23 @@ class Graph:
         _check(load_library().lap_graph_copy_csr(self._h, _ptr(rp), _ptr(col), _ptr(old)))
         return rp, col, old
 
-    def _args(self, omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s):
+    def _args(self, omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s,
+              schedule=0):
         return C.SampleArgs(n_samples=int(omega), seed=int(seed), root=int(root), stream=int(stream_id),
                             qid=int(qid), want=int(want), n_blocks=int(B), sample_begin=int(sample_begin),
                             n_total=int(n_total), mode=int(mode), pool=int(pool),
-                            timeout_s=float(timeout_s) if timeout_s else _default_timeout())
+                            timeout_s=float(timeout_s) if timeout_s else _default_timeout(),
+                            schedule=int(schedule))
 
     def sample_forests(self, omega, seed, root=-1, *, y1=True, y2=False, y2_pi=False, per_sample=True,
                        B=1, keep=(), sample_begin=0, n_total=0, mode=0, pool=0, stream_id=0, qid=0,
-                       timeout_s=0.0, stream=None):
+                       timeout_s=0.0, schedule=0, stream=None):
         """Integer counts of lap_sample_forests as numpy arrays."""
         n = self.n
         want = ((C.LAP_WANT_Y1 if y1 else 0) | (C.LAP_WANT_Y2_UNIFORM if y2 else 0)
                 | (C.LAP_WANT_Y2_PI if y2_pi else 0) | (C.LAP_WANT_PER_SAMPLE if per_sample else 0))
-        a = self._args(omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s)
+        a = self._args(omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s,
+                       schedule)
         keep = np.ascontiguousarray(np.asarray(list(keep), np.int64))
         nk = len(keep)
         out = dict(
@@ -170,6 +173,15 @@ class Graph:
                             "rw_betweenness")})
         _check(load_library().lap_estimate(self._h, ctypes.byref(a), ctypes.byref(e), _stream(stream)))
         return res
+
+    def landmark_traces(self, roots, omega, seed, stream=None):
+        """Tr((I-P_v)^{-1}) estimate (mean Wilson draws) and its SE for each root."""
+        roots = np.ascontiguousarray(roots, np.int32)
+        tr = np.zeros(len(roots))
+        se = np.zeros(len(roots))
+        _check(load_library().lap_landmark_traces(self._h, _ptr(roots), len(roots), int(omega), int(seed), _ptr(tr),
+                                                  _ptr(se), _stream(stream)))
+        return tr, se
 
     def last_stats(self):
         vals = [ctypes.c_int64() for _ in range(8)]

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchParams p) {
             c.err = p.err;
             c.t0 = t0;
             c.deadline = p.deadline;
+            c.scan_offset = 0;
             uint32_t ep = 0;
             bool ok = true;
             for (int64_t s = bi.first; s < bi.first + bi.count && ok; ++s) {

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -371,3 +372,92 @@ extern "C" int lap_batch_stats(const lap_batch *b, int64_t *wilson_steps, int64_
 }
 
 extern "C" void lap_batch_free(lap_batch *b) { delete b; }
+
+// ------------------------------------------------------------ landmark study
+// Tr((I - P_v)^{-1}) for many candidate roots of one graph: every root is a
+// job of the batched kernel that shares the graph's arrays (node and column
+// offsets 0) and runs Wilson samples only.
+extern "C" int lap_landmark_traces(lap_graph *g, const int32_t *roots, int32_t n_roots, int64_t omega, uint64_t seed,
+                                   double *trace, double *trace_se, void *hip_stream) {
+    if (!g || !roots || n_roots < 1 || omega < 1 || !trace) return fail(LAP_EINVAL, "bad landmark arguments");
+    const int64_t n = g->csr.n, nnz = g->csr.rp[n];
+    if ((int64_t)n_roots * omega >= ((int64_t)1 << 40)) return fail(LAP_EINVAL, "too many samples");
+    std::vector<BatchJobDev> jobs((size_t)n_roots);
+    for (int32_t j = 0; j < n_roots; ++j) {
+        if (roots[j] < 0 || roots[j] >= n) return fail(LAP_EINVAL, "root out of range");
+        BatchJobDev &d = jobs[j];
+        std::memset(&d, 0, sizeof d);
+        d.n = n;
+        d.nnz = nnz;
+        d.omega = omega;
+        d.sample_off = (int64_t)j * omega;
+        d.root = roots[j];
+        d.k0 = seed;
+        d.k1 = (uint64_t)(uint32_t)roots[j];
+    }
+    // Wilson chunks of about 2^17 node-samples each
+    std::vector<BatchItem> items;
+    const int64_t per = std::max<int64_t>(1, ((int64_t)1 << 17) / std::max<int64_t>(n, 1));
+    for (int32_t j = 0; j < n_roots; ++j)
+        for (int64_t s = 0; s < omega; s += per) items.push_back({j, 0, s, std::min(per, omega - s)});
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t waves = std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), 16 * (int64_t)g->n_cu));
+    DevBuf d_jobs, d_items, d_counter, d_state, d_y1, d_y1s, d_err, d_stats;
+    auto cleanup = [&]() {
+        DevBuf *b[] = {&d_jobs, &d_items, &d_counter, &d_state, &d_y1, &d_y1s, &d_err, &d_stats};
+        for (DevBuf *x : b) x->release();
+    };
+    if (d_jobs.ensure(sizeof(BatchJobDev) * jobs.size()) || d_items.ensure(sizeof(BatchItem) * items.size()) ||
+        d_counter.ensure(8) || d_state.ensure(8 * (size_t)waves * (size_t)n) || d_y1.ensure(8 * (size_t)n) ||
+        d_y1s.ensure(8 * (size_t)n_roots * (size_t)omega) || d_err.ensure(sizeof(DevErr)) ||
+        d_stats.ensure(8 * kNumStats)) {
+        cleanup();
+        return fail(LAP_ENOMEM, "cannot allocate landmark-study buffers");
+    }
+    BatchParams p;
+    std::memset(&p, 0, sizeof p);
+    p.jobs = d_jobs.as<BatchJobDev>();
+    p.items = d_items.as<BatchItem>();
+    p.n_items = (int64_t)items.size();
+    p.counter = d_counter.as<unsigned long long>();
+    p.nbr = g->nbr.as<uint64_t>();
+    p.col = g->col.as<int32_t>();
+    p.state = d_state.as<uint64_t>();
+    p.max_n = n;
+    p.y1 = d_y1.as<unsigned long long>();
+    p.y2 = d_y1.as<unsigned long long>();
+    p.y1s = d_y1s.as<int64_t>();
+    p.stats = d_stats.as<unsigned long long>();
+    p.err = d_err.as<DevErr>();
+    p.deadline = (uint64_t)(300.0 * g->clock_khz * 1000.0);
+    int rc = LAP_OK;
+    std::vector<int64_t> y((size_t)n_roots * omega);
+    DevErr e{0, 0};
+    if (hipMemcpyAsync(d_jobs.ptr, jobs.data(), sizeof(BatchJobDev) * jobs.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d_items.ptr, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_fill_u64(d_counter.as<uint64_t>(), 0, 1, s) != hipSuccess ||
+        launch_fill_u64(d_err.as<uint64_t>(), 0, 1, s) != hipSuccess ||
+        launch_fill_u64(d_stats.as<uint64_t>(), 0, kNumStats, s) != hipSuccess ||
+        launch_batch(p, waves, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(&e, d_err.ptr, sizeof e, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(y.data(), d_y1s.ptr, 8 * y.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = fail(LAP_EDEVICE, "landmark-study launch failed");
+    } else if (e.code != kErrNone) {
+        rc = fail(LAP_ERANGE, "landmark-study kernel stopped (time limit or inconsistent state)");
+    } else {
+        for (int32_t j = 0; j < n_roots; ++j) {
+            int64_t sum = 0;  // exact: below 2^53 for any run that fits the time limit
+            for (int64_t i = 0; i < omega; ++i) sum += y[(size_t)j * omega + i];
+            const double mean = (double)sum / (double)omega;
+            double sq = 0;
+            for (int64_t i = 0; i < omega; ++i) {
+                const double dd = (double)y[(size_t)j * omega + i] - mean;
+                sq += dd * dd;
+            }
+            trace[j] = mean;
+            if (trace_se) trace_se[j] = omega > 1 ? std::sqrt(sq / (double)(omega - 1)) / std::sqrt((double)omega) : NAN;
+        }
+    }
+    cleanup();
+    return rc;
+}

@@ -272,6 +272,7 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         wp.stats = g->stats.as<unsigned long long>();
         wp.err = g->err.as<DevErr>();
         wp.deadline = deadline;
+        wp.scan_offset = n > 0 ? ((a->schedule % n) + n) % n : 0;
         if (r.mode == LAP_MODE_LANE) {
             tm.begin("wilson_lane", s);
             HIP_TRY(launch_wilson_lane(wp, r.slots, s));

@@ -106,6 +106,7 @@ struct WilsonParams {
     unsigned long long *stats;     // [kNumStats]
     DevErr *err;
     uint64_t deadline;             // wall_clock64() ticks a kernel may run before it stops
+    int64_t scan_offset;           // wave form: first node the scan visits, in [0, n)
 };
 
 // One wave-cooperative Wilson sample (the device function shared by the plain
@@ -123,6 +124,7 @@ struct WaveSampleArgs {
     int32_t *keep_next, *keep_draws;   // [n] exports of this sample, or null
     DevErr *err;
     uint64_t t0, deadline;
+    int64_t scan_offset;           // start position of the scan, in [0, n)
 };
 
 struct WaveStats {

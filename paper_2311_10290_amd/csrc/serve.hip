@@ -51,6 +51,7 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeParams p) {
             c.err = p.err;
             c.t0 = t0;
             c.deadline = p.deadline;
+            c.scan_offset = 0;
             bool ok = true;
             for (int64_t s = q.first; s < q.first + q.count && ok; ++s) {
                 ep ^= 1u;

@@ -88,7 +88,12 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         if (c.keep_draws) c.keep_draws[c.root] = 0;
     }
 
-    int64_t cursor = 0;        // next node id the scan looks at (wave-uniform)
+    // the scan visits positions 0..n-1; position p is node (p + scan_offset) mod n
+    // (any offset gives the same counts: a schedule knob for race tests)
+    int64_t cursor = 0;        // next scan position (wave-uniform)
+    const int64_t off = c.scan_offset;
+    auto node_at = [&](int64_t p) -> int64_t { const int64_t q = p + off; return q >= n ? q - n : q; };
+    auto pos_of = [&](int64_t x) -> int64_t { const int64_t q = x - off; return q < 0 ? q + n : q; };
     int rev_n = 0;             // entries in rev[] (wave-uniform)
     bool overflow = false;     // rev[] overflowed: rescan needed (wave-uniform)
     int64_t tree_local = (lane == 0) ? 1 : 0;
@@ -233,8 +238,9 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         for (int q = 0; q < kScanChunks; ++q) {
             const int64_t sc = cursor + q * kWave + lane;
             const bool ld = q < scan_chunks && sc < n;
-            sc_st[q] = ld ? st[sc] : 0ull;
-            sc_nb[q] = ld ? c.nbr[sc] : 0ull;
+            const int64_t nd = ld ? node_at(sc) : 0;
+            sc_st[q] = ld ? st[nd] : 0ull;
+            sc_nb[q] = ld ? c.nbr[nd] : 0ull;
         }
 
         // ---- C. advance every walker by what its loads returned
@@ -362,7 +368,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                     const int qq = base + __popcll(m[q] & below);
                     const int64_t sc = cursor + q * kWave + lane;
                     if (f && qq < need) {
-                        sh.cand_node[qq] = (int32_t)sc;
+                        sh.cand_node[qq] = (int32_t)node_at(sc);
                         sh.cand_st[qq] = sc_st[q];
                         sh.cand_nb[qq] = sc_nb[q];
                     }
@@ -471,7 +477,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         }
 
         // ---- released nodes: free words; those behind the scan go on the revisit list
-        push_round(push && pushed < cursor, pushed);
+        push_round(push && pos_of(pushed) < cursor, pushed);
         if (__ballot(rel_hi > rel_lo)) {
             for (int j = 0; j < kStackDepth; ++j) {
                 const bool act = j >= rel_lo && j < rel_hi;
@@ -480,7 +486,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                     node = sh.stk_node[j][lane];
                     st[node] = st_pack(-1, sh.stk_k[j][lane], kTagFree, ep);
                 }
-                push_round(act && node < cursor, node);
+                push_round(act && pos_of(node) < cursor, node);
             }
         }
         fresh = false;

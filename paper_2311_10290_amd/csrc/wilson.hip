@@ -145,6 +145,7 @@ __global__ __launch_bounds__(64) void wilson_wave_kernel(WilsonParams p) {
     c.err = p.err;
     c.t0 = wall_clock64();
     c.deadline = p.deadline;
+    c.scan_offset = p.scan_offset;
     uint32_t ep = p.slot_epoch[slot];
     WaveStats ws;
     for (int64_t smp = slot; smp < p.n_samples; smp += gridDim.x) {

@@ -104,3 +104,22 @@ def test_batch_autotune_returns_a_working_tuning():
     b.run(t)
     for j in range(len(jobs)):
         _check_job(b, jobs, j)
+
+
+def test_landmark_traces_match_oracle_and_dense():
+    """Landmark study: per-root mean Wilson draws equal the oracle's per-sample
+    totals (bit-exact) and agree with Tr((I-P_v)^{-1}) from a dense solve."""
+    import math
+    from oracle import dense
+    from tests.gpu_common import both, er256_edges
+    n, s, d = er256_edges()
+    og, hg = both(n, s, d)
+    roots = [0, 5, 100, csr.landmark(og), 255]
+    omega = 600
+    tr, se = hg.landmark_traces(roots, omega, 13)
+    L = dense.laplacian(og)
+    for j, r in enumerate(roots):
+        w = native.wilson(og, r, omega, 13, want_y1=False)
+        assert tr[j] == int(w["y1"].sum()) / omega
+        exact = float(np.trace(dense.walk_green(L, r)))
+        assert abs(tr[j] - exact) < 4.5 * se[j]

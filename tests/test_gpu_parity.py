@@ -84,6 +84,35 @@ def test_wave_pool_sizes_and_ragged_sample_counts(pool):
     _same(got, exp, ["Y1", "y1", "next", "draws"])
 
 
+def test_schedule_rotation_does_not_change_counts():
+    """Race check: rotating where the start scan begins changes which walker
+    takes which start and the order of every claim, park and cycle pop; by
+    Wilson's stack argument the counts and trees must not change."""
+    n, s, d = ba_edges(3000, 3, 9)
+    og, hg = both(n, s, d)
+    root = csr.landmark(og)
+    exp = _oracle_counts(og, root, 150, 4, B=2, keep=[0, 149], uniform=False, pi=False)
+    for sched in (0, 1, 777, og.n - 1, 10**9 + 7):
+        log(f"schedule {sched}")
+        got = hg.sample_forests(150, 4, root, B=2, keep=[0, 149], mode=2, pool=50, schedule=sched)
+        _same(got, exp, ["Y1", "y1", "next", "draws"])
+
+
+def test_kernel_time_limit_is_reported_and_recovered():
+    """A time limit forced from the host stops the kernels through their own
+    bounded checks; the call reports LAP_ERANGE and the next call is exact."""
+    from paper_2311_10290_amd import LapError
+    n, s, d = ba_edges(200_000, 3, 2)
+    og, hg = both(n, s, d)
+    root = csr.landmark(og)
+    with pytest.raises(LapError) as ei:
+        hg.sample_forests(2048, 1, root, y2=True, timeout_s=1e-4)
+    assert ei.value.code == -5
+    got = hg.sample_forests(16, 1, root, y2=True, B=1)
+    exp = _oracle_counts(og, root, 16, 1, B=1, pi=False)
+    _same(got, exp, ["Y1", "y1", "Y2", "len_uniform"])
+
+
 def test_resume_in_two_halves_equals_one_run():
     n, s, d = er256_edges()
     og, hg = both(n, s, d)
