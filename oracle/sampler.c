@@ -314,7 +314,8 @@ int32_t oracle_absorbed(int64_t n, const int64_t *rp, const int32_t *col, int32_
         uint64_t x0 = walk_draw(k0, k1, (uint64_t)tag, (uint64_t)i, 0, 0, qid);
         int32_t s;
         if (tag == 1) s = (int32_t)oracle_map_below(x0, (uint64_t)n);
-        else s = col[oracle_map_below(x0, (uint64_t)nnz)];
+        else if (nnz > 0) s = col[oracle_map_below(x0, (uint64_t)nnz)];
+        else s = root;   /* a single node without edges: the walk is empty */
         if (start_per_walk) start_per_walk[w] = s;
         int64_t b = (int64_t)(((__int128)i * B) / omega_total);
         int32_t u = s;

@@ -64,6 +64,8 @@ extern "C" int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, con
         if (b.ensure(bytes) != LAP_OK) return LAP_ENOMEM;
         if (bytes && hipMemcpyAsync(b.ptr, src_, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
             return LAP_EDEVICE;
+        // an empty array still gets a defined (zero) placeholder word
+        if (!bytes && launch_fill_u64(b.as<uint64_t>(), 0ull, 1, s) != hipSuccess) return LAP_EDEVICE;
         return LAP_OK;
     };
     if ((rc = upload(g->rp, g->csr.rp.data(), sizeof(int64_t) * (nn + 1))) != LAP_OK ||

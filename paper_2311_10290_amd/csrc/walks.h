@@ -21,7 +21,10 @@ static inline __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag,
                                         DevErr *err, uint64_t t0, uint64_t deadline) {
     const uint64_t c0 = (uint64_t)i | ((uint64_t)tag << 56);
     const uint64_t x0 = philox_w0(c0, 0, 0, g.qid, g.k0, g.k1);
-    int32_t u = (tag == 1) ? (int32_t)pick_below(x0, (uint64_t)g.n) : g.col[pick_below(x0, (uint64_t)g.nnz)];
+    // a graph without edges is the single node v: the walk starts (and ends) there
+    int32_t u = (tag == 1)      ? (int32_t)pick_below(x0, (uint64_t)g.n)
+                : (g.nnz > 0)   ? g.col[pick_below(x0, (uint64_t)g.nnz)]
+                                : g.root;
     int64_t len = 0;
     while (u != g.root) {
         const uint64_t nb = g.nbr[u];

@@ -96,3 +96,12 @@ def test_loop_included_path_only_uses_drawn_entries():
             p = native.loop_included_path(g.n, v, s, g=g, sample=q, seed=8)
             uses = np.bincount(p[:-1], minlength=g.n)
             assert (uses <= r["draws"][q]).all()
+
+
+def test_single_node_graph_walks_are_empty():
+    """One node, no edges: both kinds of walk start at v and have length 0,
+    so Kemeny's constant of a single node is 0 (Sec. 2, empty spectrum sum)."""
+    g = csr.build_csr(1, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    for tag in (1, 2):
+        a = native.absorbed(g, 0, 16, 1, tag)
+        assert (a["len"] == 0).all() and (a["Y2"] == 0).all()
