@@ -215,11 +215,12 @@ def bench_large(lap, gg, peaks):
     dt = (time.perf_counter() - t) / reps
     lap.prof_enable(False)
     st = g.last_stats()
-    ms_w, n_w = lap.prof_read("wilson_wave")
+    kern = "wilson_group" if lap.prof_read("wilson_group")[1] else "wilson_wave"
+    ms_w, n_w = lap.prof_read(kern)
     wave_s = ms_w / max(n_w, 1) * 1e-3
     loads = LOADS_PER_WILSON_STEP * st["wilson_steps"] / wave_s
     res = {"workload": "R-MAT scale 22 LCC, root = max degree, 512 trees + 512 walks of each kind",
-           "n": g.n, "nnz": g.nnz, "omega": omega, "s_per_step": dt,
+           "n": g.n, "nnz": g.nnz, "omega": omega, "s_per_step": dt, "kernel": kern,
            "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) / dt,
            "trees_per_s": omega / dt, "wilson_steps_per_tree": st["wilson_steps"] / omega,
            "wilson_kernel_s": wave_s, "wilson_loads_per_s": loads,

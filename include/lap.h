@@ -94,9 +94,11 @@ enum {
 };
 
 enum {
-    LAP_MODE_AUTO = 0,        /* wave-cooperative walker pool */
+    LAP_MODE_AUTO = 0,        /* the wave form, or the workgroup form when too few samples to fill
+                                 the device run on a large graph */
     LAP_MODE_LANE = 1,        /* one lane per sample, walks run one after another */
-    LAP_MODE_WAVE = 2         /* one wavefront per sample, 64 concurrent walkers */
+    LAP_MODE_WAVE = 2,        /* one wavefront per sample, 64 concurrent walkers */
+    LAP_MODE_GROUP = 3        /* one workgroup of 2, 4 or 8 wavefronts per sample, 64 walkers each */
 };
 
 typedef struct {
@@ -113,8 +115,9 @@ typedef struct {
     int32_t mode;          /* LAP_MODE_* */
     int32_t pool;          /* concurrent samples (slots); 0 = automatic */
     double timeout_s;      /* kernel time limit; 0 = 120 s */
-    int64_t schedule;      /* wave form: the start scan begins at node (schedule mod n) and wraps;
-                              counts do not depend on it (a knob for schedule-randomised tests) */
+    int64_t schedule;      /* wave and workgroup forms: the start scan begins at node (schedule mod n)
+                              and wraps; counts do not depend on it (a knob for schedule-randomised tests) */
+    int32_t group;         /* workgroup form: wavefronts per sample (2, 4 or 8); 0 = automatic */
 } lap_sample_args;
 
 typedef struct {
@@ -343,8 +346,8 @@ const char *lap_last_error(void);
 /* Kernel timing: when enabled, every kernel launch of the library is
  * bracketed by HIP events on the stream it runs on; lap_prof_read returns
  * the accumulated milliseconds and launch count for a kernel name
- * ("wilson_wave", "wilson_lane", "absorbed", "assemble", "batch",
- * "batch_assemble").  Returns
+ * ("wilson_wave", "wilson_lane", "wilson_group", "absorbed", "assemble",
+ * "batch", "batch_assemble").  Returns
  * LAP_EINVAL for an unknown name. */
 int lap_prof_enable(int on);
 int lap_prof_reset(void);

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "liblap.so")
 LAP_OK, LAP_EINVAL, LAP_ENOTCONN, LAP_ENOMEM, LAP_EDEVICE, LAP_ERANGE = 0, -1, -2, -3, -4, -5
 LAP_KEEP_LCC = 1
 LAP_WANT_Y1, LAP_WANT_Y2_UNIFORM, LAP_WANT_Y2_PI, LAP_WANT_PER_SAMPLE, LAP_OUT_DEVICE = 1, 2, 4, 8, 16
-LAP_MODE_AUTO, LAP_MODE_LANE, LAP_MODE_WAVE = 0, 1, 2
+LAP_MODE_AUTO, LAP_MODE_LANE, LAP_MODE_WAVE, LAP_MODE_GROUP = 0, 1, 2, 3
 
 # every symbol include/lap.h declares
 EXPORTS = [
@@ -33,7 +33,7 @@ class SampleArgs(ctypes.Structure):
         ("stream", ctypes.c_uint32), ("qid", ctypes.c_uint64), ("want", ctypes.c_uint32),
         ("n_blocks", ctypes.c_int32), ("sample_begin", ctypes.c_int64), ("n_total", ctypes.c_int64),
         ("mode", ctypes.c_int32), ("pool", ctypes.c_int32), ("timeout_s", ctypes.c_double),
-        ("schedule", ctypes.c_int64),
+        ("schedule", ctypes.c_int64), ("group", ctypes.c_int32),
     ]
 
 

@@ -119,7 +119,7 @@ namespace {
 
 struct Resolved {
     int64_t omega, begin, total;
-    int32_t root, B, mode;
+    int32_t root, B, mode, group;
     int64_t slots;
     bool wilson, y2u, y2p;
 };
@@ -132,7 +132,9 @@ int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, c
     if (a->root < -1 || a->root >= n) return fail(LAP_EINVAL, "root out of range");
     if (a->n_blocks < 1) return fail(LAP_EINVAL, "n_blocks must be >= 1");
     if (a->sample_begin < 0) return fail(LAP_EINVAL, "sample_begin must be >= 0");
-    if (a->mode < LAP_MODE_AUTO || a->mode > LAP_MODE_WAVE) return fail(LAP_EINVAL, "unknown mode");
+    if (a->mode < LAP_MODE_AUTO || a->mode > LAP_MODE_GROUP) return fail(LAP_EINVAL, "unknown mode");
+    if (a->group != 0 && a->group != 2 && a->group != 4 && a->group != 8)
+        return fail(LAP_EINVAL, "group must be 0, 2, 4 or 8");
     if (a->pool < 0) return fail(LAP_EINVAL, "pool must be >= 0");
     if (a->want & ~(uint32_t)(LAP_WANT_Y1 | LAP_WANT_Y2_UNIFORM | LAP_WANT_Y2_PI | LAP_WANT_PER_SAMPLE |
                               LAP_OUT_DEVICE))
@@ -150,13 +152,29 @@ int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, c
             return fail(LAP_EINVAL, "keep_idx entries must be sample indices of this call");
     r.root = a->root < 0 ? g->max_deg_node : a->root;
     r.B = a->n_blocks;
-    r.mode = a->mode == LAP_MODE_AUTO ? LAP_MODE_WAVE : a->mode;
+    // the device holds 16 sample waves per CU; with fewer samples than that on
+    // a large graph, several waves share a sample instead (workgroup form)
+    const int64_t wave_slots = (int64_t)g->n_cu * 16;
+    r.mode = a->mode;
+    if (r.mode == LAP_MODE_AUTO)
+        r.mode = (r.omega * 4 <= wave_slots && n >= (1 << 16)) ? LAP_MODE_GROUP : LAP_MODE_WAVE;
+    r.group = 0;
+    if (r.mode == LAP_MODE_GROUP) {
+        r.group = a->group;
+        if (r.group == 0) {
+            r.group = 2;
+            while (r.group < 8 && r.omega * r.group * 2 <= wave_slots) r.group *= 2;
+        }
+    }
     // concurrent sample slots: bounded by the samples, the pool and a state
     // budget of 48 GiB (8 bytes per node per slot)
     const int64_t per_slot = 8 * std::max<int64_t>(n, 1);
     const int64_t budget = ((int64_t)48 << 30) / per_slot;
     int64_t pool = a->pool;
-    if (pool == 0) pool = r.mode == LAP_MODE_LANE ? (int64_t)g->n_cu * 256 : (int64_t)g->n_cu * 16;
+    if (pool == 0)
+        pool = r.mode == LAP_MODE_LANE    ? (int64_t)g->n_cu * 256
+               : r.mode == LAP_MODE_GROUP ? wave_slots / r.group
+                                          : wave_slots;
     r.slots = std::max<int64_t>(1, std::min({r.omega, pool, budget}));
     return LAP_OK;
 }
@@ -278,6 +296,9 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         if (r.mode == LAP_MODE_LANE) {
             tm.begin("wilson_lane", s);
             HIP_TRY(launch_wilson_lane(wp, r.slots, s));
+        } else if (r.mode == LAP_MODE_GROUP) {
+            tm.begin("wilson_group", s);
+            HIP_TRY(launch_wilson_group(wp, r.slots, r.group, s));
         } else {
             tm.begin("wilson_wave", s);
             HIP_TRY(launch_wilson_wave(wp, r.slots, s));

@@ -45,25 +45,27 @@ __device__ __forceinline__ uint32_t nbr_deg(uint64_t r) { return (uint32_t)(r >>
 // ------------------------------------------------------------ per-node walk state
 // One 64-bit word per node per sample slot:
 //   bits  0..31  next   (last draw at the node: its stack top)
-//   bits 32..55  k      (draws made at the node in this sample)
-//   bits 56..62  tag    (0 free, 1..64 on the path of walker lane tag-1, 127 in tree)
+//   bits 32..52  k      (draws made at the node in this sample)
+//   bits 53..62  tag    (0 free, 1..512 on the path of walker tag-1 of the
+//                        sample's wave or workgroup, 1023 in tree)
 //   bit  63      epoch  (parity of the slot's sample counter; a word from the
 //                        previous sample reads as free with k = 0)
 constexpr uint32_t kTagFree = 0;
-constexpr uint32_t kTagTree = 127;
-constexpr uint32_t kMaxDraws = (1u << 24) - 1;
+constexpr uint32_t kTagTree = 1023;
+constexpr uint32_t kMaxWalkers = 512;
+constexpr uint32_t kMaxDraws = (1u << 21) - 1;
 
 __device__ __forceinline__ uint64_t st_pack(int32_t nxt, uint32_t k, uint32_t tag, uint32_t ep) {
-    return (uint64_t)(uint32_t)nxt | ((uint64_t)k << 32) | ((uint64_t)tag << 56) |
+    return (uint64_t)(uint32_t)nxt | ((uint64_t)k << 32) | ((uint64_t)tag << 53) |
            ((uint64_t)ep << 63);
 }
 __device__ __forceinline__ bool st_current(uint64_t w, uint32_t ep) { return (uint32_t)(w >> 63) == ep; }
 __device__ __forceinline__ int32_t st_next(uint64_t w) { return (int32_t)(uint32_t)w; }
 __device__ __forceinline__ uint32_t st_k(uint64_t w, uint32_t ep) {
-    return st_current(w, ep) ? (uint32_t)((w >> 32) & 0xFFFFFFu) : 0u;
+    return st_current(w, ep) ? (uint32_t)((w >> 32) & 0x1FFFFFu) : 0u;
 }
 __device__ __forceinline__ uint32_t st_tag(uint64_t w, uint32_t ep) {
-    return st_current(w, ep) ? (uint32_t)((w >> 56) & 0x7Fu) : kTagFree;
+    return st_current(w, ep) ? (uint32_t)((w >> 53) & 0x3FFu) : kTagFree;
 }
 
 // ------------------------------------------------------------ error reporting

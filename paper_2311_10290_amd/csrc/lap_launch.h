@@ -10,6 +10,7 @@ namespace lap {
 
 hipError_t launch_wilson_lane(const WilsonParams &p, int64_t slots, hipStream_t s);
 hipError_t launch_wilson_wave(const WilsonParams &p, int64_t slots, hipStream_t s);
+hipError_t launch_wilson_group(const WilsonParams &p, int64_t slots, int waves, hipStream_t s);
 hipError_t launch_absorbed(const AbsorbedParams &p, hipStream_t s);
 
 // Fill n 64-bit words with a value (used instead of hipMemsetAsync so the

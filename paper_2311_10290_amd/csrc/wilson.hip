@@ -37,6 +37,7 @@
 // (lap_sample_forests) or assembled.
 #include "lap_device.h"
 #include "lap_launch.h"
+#include "group_sample.h"
 #include "wave_sample.h"
 
 namespace lap {
@@ -168,6 +169,50 @@ __global__ __launch_bounds__(64) void wilson_wave_kernel(WilsonParams p) {
     flush_wave_stats(ws, p.stats);
 }
 
+// ------------------------------------------------------------ workgroup form
+// W wavefronts per sample (group_sample.h); one workgroup per slot.
+// (at least 4 waves per SIMD: 16 per CU, as in the wave form)
+template <int W>
+__global__ __launch_bounds__(kWave * W, 4) void wilson_group_kernel(WilsonParams p) {
+    __shared__ GroupShared<W> sh;
+    const int tid = (int)threadIdx.x;
+    const int64_t slot = blockIdx.x;
+    WaveSampleArgs c;
+    c.n = p.n;
+    c.nnz = p.nnz;
+    c.nbr = p.nbr;
+    c.col = p.col;
+    c.root = p.root;
+    c.k0 = p.k0;
+    c.k1 = p.k1;
+    c.qid = p.qid;
+    c.st = p.state + slot * p.n;
+    c.err = p.err;
+    c.t0 = wall_clock64();
+    c.deadline = p.deadline;
+    c.scan_offset = p.scan_offset;
+    uint32_t ep = p.slot_epoch[slot];
+    WaveStats ws;
+    for (int64_t smp = slot; smp < p.n_samples; smp += gridDim.x) {
+        const int64_t sample = p.sample_begin + smp;
+        ep ^= 1u;
+        const int keep_q = find_keep(p, sample);
+        c.sample = sample;
+        c.ep = ep;
+        c.y1b = p.y1 ? p.y1 + block_of(sample, p.n_blocks, p.n_total) * p.n : nullptr;
+        c.keep_next = (keep_q >= 0 && p.next_out) ? p.next_out + (int64_t)keep_q * p.n : nullptr;
+        c.keep_draws = (keep_q >= 0 && p.draws_out) ? p.draws_out + (int64_t)keep_q * p.n : nullptr;
+        int64_t y1 = 0;
+        if (!group_wilson_sample<W>(c, sh, &y1, ws)) break;
+        if (tid == 0) {
+            if (p.y1_per_sample) p.y1_per_sample[smp] = y1;
+            ++ws.trees;
+        }
+    }
+    if (tid == 0) p.slot_epoch[slot] = ep;
+    flush_group_stats(ws, p.stats);
+}
+
 // ----------------------------------------------------------------- launchers
 hipError_t launch_wilson_lane(const WilsonParams &p, int64_t slots, hipStream_t s) {
     const int bs = 64;
@@ -178,6 +223,27 @@ hipError_t launch_wilson_lane(const WilsonParams &p, int64_t slots, hipStream_t 
 
 hipError_t launch_wilson_wave(const WilsonParams &p, int64_t slots, hipStream_t s) {
     hipLaunchKernelGGL(wilson_wave_kernel, dim3((unsigned)slots), dim3(kWave), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace lap
+
+namespace lap {
+
+hipError_t launch_wilson_group(const WilsonParams &p, int64_t slots, int waves, hipStream_t s) {
+    switch (waves) {
+    case 2:
+        hipLaunchKernelGGL(wilson_group_kernel<2>, dim3((unsigned)slots), dim3(kWave * 2), 0, s, p);
+        break;
+    case 4:
+        hipLaunchKernelGGL(wilson_group_kernel<4>, dim3((unsigned)slots), dim3(kWave * 4), 0, s, p);
+        break;
+    case 8:
+        hipLaunchKernelGGL(wilson_group_kernel<8>, dim3((unsigned)slots), dim3(kWave * 8), 0, s, p);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

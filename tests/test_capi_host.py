@@ -75,3 +75,32 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(api, "_lib", None)
     with pytest.raises(ImportError):
         api.load_library()
+
+
+STRUCTS = {"SampleArgs": "lap_sample_args", "Counts": "lap_counts", "Estimates": "lap_estimates",
+           "BatchJob": "lap_batch_job", "BatchTuning": "lap_batch_tuning", "BatchOut": "lap_batch_out",
+           "Query": "lap_query", "QueryResult": "lap_query_result", "ServerConfig": "lap_server_config"}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror has the C struct's size and field offsets (the
+    header compiled by the host C compiler)."""
+    import subprocess
+    from paper_2311_10290_amd import _capi
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lap.h"', 'int main(void) {']
+    for py, c in STRUCTS.items():
+        lines.append(f'printf("{py} size %zu\\n", sizeof({c}));')
+        for f, _ in getattr(_capi, py)._fields_:
+            lines.append(f'printf("{py} {f} %zu\\n", offsetof({c}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for py in STRUCTS:
+        cls = getattr(_capi, py)
+        assert got[(py, "size")] == ctypes.sizeof(cls), py
+        for f, _ in cls._fields_:
+            assert got[(py, f)] == getattr(cls, f).offset, (py, f)
