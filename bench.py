@@ -189,6 +189,22 @@ def _replay(lap, srv, qs, qid0):
     return lat, wall, bad
 
 
+def _serial(lap, srv, qs, qid0):
+    """The same queries one at a time: each is submitted when the previous
+    one has completed (no batching across queries).  Returns the wall time."""
+    kinds = {0: lap.Server.CLOSENESS, 1: lap.Server.RESISTANCE, 2: lap.Server.KEMENY}
+    t0 = time.perf_counter()
+    bad = 0
+    for q in qs:
+        srv.submit(qid0 + q["qid"], kinds[q["kind"]], q["budget"], q["u"], q["w"])
+        done = []
+        while not done:
+            srv.step(wait=True)
+            done = srv.poll()
+        bad += sum(r["status"] != 0 for r in done)
+    return time.perf_counter() - t0, bad
+
+
 def bench_large(lap, gg, peaks):
     """Large plain run: R-MAT scale 22 (edge factor 16, a/b/c/d = .57/.19/.19/.05),
     symmetrised, self-loops and duplicates dropped, largest component kept;
@@ -251,10 +267,15 @@ def bench_serve(lap, gg, n_queries):
     lat, wall, bad = _replay(lap, srv, qs, 0)
     sat = n_queries / wall
     log(f"serve: saturation {sat:.1f} queries/s")
+    n_serial = min(n_queries, 100)
+    wall_serial, bad_serial = _serial(lap, srv, qs[:n_serial], 10_000_000)
+    log(f"serve: one query at a time {n_serial / wall_serial:.1f} queries/s")
     out = {"workload": "R-MAT scale 21 LCC resident; Poisson mix 45% closeness (64-1024 walks), "
                        "45% resistance (1024 walk pairs), 10% Kemeny (256 samples)",
            "n": g.n, "nnz": g.nnz, "queries": n_queries, "saturation_qps": sat,
-           "closed_loop_p50_ms": float(np.percentile(lat, 50) * 1e3), "errors": int(bad), "runs": []}
+           "closed_loop_p50_ms": float(np.percentile(lat, 50) * 1e3), "errors": int(bad) + int(bad_serial),
+           "one_at_a_time_qps": n_serial / wall_serial,
+           "speedup_served_vs_one_at_a_time": sat / (n_serial / wall_serial), "runs": []}
     for k, frac in enumerate((0.5, 0.8)):
         qs = gg.query_stream(g.n, n_queries, qps=frac * sat, seed=4 + k)
         lat, wall, bad = _replay(lap, srv, qs, (k + 1) * 1_000_000)
