@@ -317,6 +317,8 @@ typedef struct {
     int32_t items_per_launch;/* 0 = 4096 */
     int32_t wilson_chunk;    /* Wilson samples per work item; 0 = 1 */
     double timeout_s;        /* kernel time limit; 0 = 300 s */
+    int32_t wilson_group;    /* wavefronts per Wilson sample in Wilson launches: 1 = wave form,
+                                2, 4 or 8 = workgroup form; 0 = 8 on graphs of >= 2^16 nodes, else 1 */
 } lap_server_config;
 
 /* Compute the cached global terms (lap_sample_forests with qid

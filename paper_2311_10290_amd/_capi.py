@@ -87,7 +87,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("root", ctypes.c_int32), ("stream", ctypes.c_uint32),
                 ("global_samples", ctypes.c_int64), ("arena_bytes", ctypes.c_int64), ("launches", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("items_per_launch", ctypes.c_int32), ("wilson_chunk", ctypes.c_int32),
-                ("timeout_s", ctypes.c_double)]
+                ("timeout_s", ctypes.c_double), ("wilson_group", ctypes.c_int32)]
 
 
 def declare(lib):

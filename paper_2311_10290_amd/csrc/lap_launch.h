@@ -45,6 +45,7 @@ hipError_t launch_kemeny(const int64_t *y1, const int64_t *len, int64_t omega, d
                          double *se, hipStream_t s);
 
 hipError_t launch_serve(const ServeParams &p, int64_t waves, hipStream_t s);
+hipError_t launch_serve_group(const ServeParams &p, int waves, int64_t groups, hipStream_t s);
 hipError_t launch_batch(const BatchParams &p, int64_t waves, hipStream_t s);
 hipError_t launch_batch_assemble(const BatchParams &p, int32_t n_jobs, hipStream_t s);
 

@@ -306,7 +306,13 @@ int launch(lap_server *s, int idx) {
     p.stats = s->stats.as<unsigned long long>();
     p.err = L.err.as<DevErr>();
     p.deadline = s->deadline;
-    HIP_TRY(launch_serve(p, std::min<int64_t>(s->cfg.waves, cnt), L.s));
+    if (cls == 1 && s->cfg.wilson_group > 1) {
+        // a Wilson-only launch: W wavefronts per sample, one workgroup per state
+        // slot of the launch
+        HIP_TRY(launch_serve_group(p, s->cfg.wilson_group, std::min<int64_t>(s->cfg.waves, cnt), L.s));
+    } else {
+        HIP_TRY(launch_serve(p, std::min<int64_t>(s->cfg.waves, cnt), L.s));
+    }
     HIP_TRY(hipEventRecord(L.ev, L.s));
     L.busy = true;
     return LAP_OK;
@@ -323,7 +329,9 @@ extern "C" int lap_server_create(lap_graph *g, const lap_server_config *cfg, voi
     if (cfg) s->cfg = *cfg;
     lap_server_config &c = s->cfg;
     if (c.root < -1 || c.root >= s->n || c.global_samples < 0 || c.arena_bytes < 0 || c.launches < 0 ||
-        c.waves < 0 || c.items_per_launch < 0 || c.wilson_chunk < 0) {
+        c.waves < 0 || c.items_per_launch < 0 || c.wilson_chunk < 0 ||
+        (c.wilson_group != 0 && c.wilson_group != 1 && c.wilson_group != 2 && c.wilson_group != 4 &&
+         c.wilson_group != 8)) {
         delete s;
         return fail(LAP_EINVAL, "bad server configuration");
     }
@@ -335,6 +343,7 @@ extern "C" int lap_server_create(lap_graph *g, const lap_server_config *cfg, voi
     if (c.items_per_launch == 0) c.items_per_launch = 4096;
     if (c.wilson_chunk == 0) c.wilson_chunk = 1;
     if (c.timeout_s <= 0) c.timeout_s = 300.0;
+    if (c.wilson_group == 0) c.wilson_group = s->n >= (1 << 16) ? 8 : 1;
     s->k1 = ((uint64_t)c.stream << 32) | (uint64_t)(uint32_t)c.root;
     s->deadline = (uint64_t)(c.timeout_s * g->clock_khz * 1000.0);
     // cached global terms: Tr(L_v^{-1}) and 1^T L_v^{-1} 1 from one Wilson +

@@ -64,10 +64,12 @@ def _run(hg, qs, **cfg):
     return {r["qid"]: r for r in res}, g
 
 
-def test_server_matches_oracle():
+@pytest.mark.parametrize("wilson_group", [1, 8])
+def test_server_matches_oracle(wilson_group):
+    """wilson_group 1: Kemeny trees by single wavefronts; 8: by workgroups of 8."""
     og, hg, root, qs = _setup()
-    log("serve: mixed run")
-    res, (tr_lv, s_lv) = _run(hg, qs)
+    log(f"serve: mixed run, wilson_group {wilson_group}")
+    res, (tr_lv, s_lv) = _run(hg, qs, wilson_group=wilson_group)
     w = native.wilson(og, root, 512, SEED, qid=GLOBAL_QID)
     a = native.absorbed(og, root, 512, SEED, 1, qid=GLOBAL_QID)
     otr, os_ = estimators.globals_from_counts(w["Y1"][0], a["Y2"][0], 512, og.deg, root)
@@ -81,9 +83,10 @@ def test_alone_equals_mixed_under_any_batching():
     og, hg, root, qs = _setup()
     mixed, _ = _run(hg, qs)
     odd, _ = _run(hg, qs, launches=1, items_per_launch=3, waves=5)
+    grouped, _ = _run(hg, qs, launches=4, items_per_launch=5, waves=3, wilson_group=4)
     for q in qs:
-        alone, _ = _run(hg, [q], launches=3, items_per_launch=2)
-        for other in (mixed, odd):
+        alone, _ = _run(hg, [q], launches=3, items_per_launch=2, wilson_group=2)
+        for other in (mixed, odd, grouped):
             assert alone[q["qid"]]["value"] == other[q["qid"]]["value"], q
             assert alone[q["qid"]]["se"] == other[q["qid"]]["se"] or np.isnan(alone[q["qid"]]["se"])
 
