@@ -113,3 +113,23 @@ def resistance_query(ss, st, tt, ts, d_s, d_t):
          + np.asarray(tt, np.float64) / d_t - np.asarray(ts, np.float64) / d_s)
     b = len(r)
     return float(math.fsum(r.tolist()) / b), (float(r.std(ddof=1) / math.sqrt(b)) if b > 1 else float("nan"))
+
+
+def spantree_diag(X1, X2, omega, n):
+    """SpanTree estimate of diag(L^dagger) (Alg. 1, last loop):
+    x1(u) - 2 x2(u) + (1/n) sum_w x2(w), where x1 = X1 / omega and
+    x2 = X2 / (n omega) (X2 counts the path support in units of 1/n)."""
+    x1 = np.asarray(X1, np.float64) / omega
+    x2 = np.asarray(X2, np.float64) / (n * omega)
+    return x1 - 2.0 * x2 + math.fsum(x2.tolist()) / n
+
+
+def spantree_kemeny(s1, s2, two_m):
+    """SpanTree estimate of Kemeny's constant (Alg. 3): the mean over
+    samples of s1 - s2 / 2m (s2 counts the path support in units of 1/2m),
+    and its standard error."""
+    z = np.asarray(s1, np.float64) - np.asarray(s2, np.float64) / two_m
+    omega = len(z)
+    est = math.fsum(z.tolist()) / omega
+    se = float(z.std(ddof=1) / math.sqrt(omega)) if omega > 1 else float("nan")
+    return est, se

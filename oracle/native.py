@@ -55,6 +55,12 @@ def lib():
         L.oracle_query_walks.argtypes = [i64, P, P, i32, u64, u32, u64, i32, i32, i32, i32, i64, i64,
                                          P, P, P, P]
         L.oracle_query_walks.restype = i32
+        L.oracle_bfs_tree.argtypes = [i64, P, P, i32, P]
+        L.oracle_bfs_tree.restype = i64
+        L.oracle_spantree_tree.argtypes = [i64, P, i32, P, P, P, P, P, P, P]
+        L.oracle_spantree_tree.restype = None
+        L.oracle_spantree.argtypes = [i64, P, P, i32, u64, u32, u64, i64, i64, i32, P, P, P, P, i32]
+        L.oracle_spantree.restype = i32
         _lib = L
     return _lib
 
@@ -187,3 +193,45 @@ def query_walks(g, root, seed, qid, start, sub, a, b, n_walks, *, stream=0, walk
     lib().oracle_query_walks(n, _p(rp), _p(col), int(root), seed, stream, qid, int(start), int(sub), int(a),
                              int(b), walk_begin, n_walks, _p(da), _p(db), _p(nl), _p(ln))
     return dict(dep_a=da, dep_b=db, norm_len=nl, len=ln)
+
+
+def bfs_tree(g, root):
+    """BFS parent array from the root (neighbours in ascending order)."""
+    n, rp, col = _graph(g)
+    par = np.zeros(n, np.int32)
+    reached = lib().oracle_bfs_tree(n, _p(rp), _p(col), int(root), _p(par))
+    if reached != n:
+        raise ValueError("graph not connected")
+    return par
+
+
+def spantree_tree(g, root, next_, weights=None, bfs_par=None):
+    """Per-tree quantities of Alg. 1 / Alg. 3 for one spanning tree next_[]:
+    path support ps, unit-flow voltage sums x1 and weighted-flow sums x2
+    (weights default to 1: Alg. 1; degrees: Alg. 3)."""
+    n = g.n
+    nxt = np.ascontiguousarray(next_, np.int32)
+    w = np.ones(n, np.int64) if weights is None else np.ascontiguousarray(weights, np.int64)
+    par = bfs_tree(g, root) if bfs_par is None else np.ascontiguousarray(bfs_par, np.int32)
+    ps = np.zeros(n, np.int64)
+    x1 = np.zeros(n, np.int64)
+    x2 = np.zeros(n, np.int64)
+    scr = np.zeros(5 * n, np.int32)
+    koff = np.zeros(n + 1, np.int64)
+    lib().oracle_spantree_tree(n, _p(nxt), int(root), _p(par), _p(w), _p(ps), _p(x1), _p(x2), _p(scr), _p(koff))
+    return dict(ps=ps, x1=x1, x2=x2, vis=scr[:n].copy(), fin=scr[n:2 * n].copy())
+
+
+def spantree(g, root, n_samples, seed, kind, *, stream=0, qid=0, sample_begin=0, threads=0):
+    """SpanTree sums over Wilson samples: kind 1 (Alg. 1) returns X1, X2 ([n]);
+    kind 2 (Alg. 3) returns per-sample s1, s2 ([n_samples])."""
+    n, rp, col = _graph(g)
+    X1 = np.zeros(n, np.int64) if kind == 1 else None
+    X2 = np.zeros(n, np.int64) if kind == 1 else None
+    s1 = np.zeros(n_samples, np.int64) if kind == 2 else None
+    s2 = np.zeros(n_samples, np.int64) if kind == 2 else None
+    st = lib().oracle_spantree(n, _p(rp), _p(col), int(root), seed, stream, qid, sample_begin, n_samples, kind,
+                               _p(X1), _p(X2), _p(s1), _p(s2), threads)
+    if st != 0:
+        raise RuntimeError(f"oracle_spantree failed ({st})")
+    return dict(X1=X1, X2=X2, s1=s1, s2=s2)

@@ -377,3 +377,169 @@ int32_t oracle_query_walks(int64_t n, const int64_t *rp, const int32_t *col, int
     }
     return 0;
 }
+
+/* ------------------------------------------------------------ SpanTree (Alg. 1, Alg. 3) */
+/* BFS tree from the root, neighbours taken in ascending order: bfs_par[u] is
+ * u's parent (-1 at the root).  Returns the number of nodes reached. */
+int64_t oracle_bfs_tree(int64_t n, const int64_t *rp, const int32_t *col, int32_t root, int32_t *bfs_par) {
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t *seen = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!queue || !seen) { free(queue); free(seen); return -1; }
+    for (int64_t i = 0; i < n; ++i) bfs_par[i] = -1;
+    int64_t head = 0, tail = 0;
+    queue[tail++] = root;
+    seen[root] = 1;
+    while (head < tail) {
+        int32_t a = queue[head++];
+        for (int64_t j = rp[a]; j < rp[a + 1]; ++j) {
+            int32_t b = col[j];
+            if (!seen[b]) { seen[b] = 1; bfs_par[b] = a; queue[tail++] = b; }
+        }
+    }
+    free(queue); free(seen);
+    return tail;
+}
+
+/*
+ * The per-tree part of Alg. 1 (weights w = 1) and Alg. 3 (w = degrees) for
+ * one spanning tree next[] rooted at `root` (next[root] = -1):
+ *   1. path support: ps[a] = sum of w[u] over the nodes u whose tree path
+ *      to the root uses the out-edge (a, next[a]) -- the flow on that edge
+ *      when w[u] enters at every u and leaves at the root (in units of 1/sum w);
+ *   2. a depth-first traversal of the tree from the root gives visit and
+ *      finish times; a is an ancestor-or-self of u iff u's interval lies in a's;
+ *   3. for every u, along the BFS path from u to the root, each edge (e1, e2)
+ *      that is a tree edge on u's own tree path (its lower end an
+ *      ancestor-or-self of u) adds the flow it carries in the direction
+ *      e1 -> e2: +1 to x1[u] and +ps[e1] to x2[u] if next[e1] = e2, -1 and
+ *      -ps[e2] if next[e2] = e1.
+ * x1[u] averages to (L_v^{-1})_uu and x2[u] / sum w to the voltage at u of the
+ * weighted system (Sec. 4.1, Sec. 5.2).  Scratch: 5n int32 and n+1 int64
+ * (child lists); vis/fin are its first two n-blocks.  x1, x2, ps are
+ * written, not accumulated.
+ */
+void oracle_spantree_tree(int64_t n, const int32_t *next, int32_t root, const int32_t *bfs_par,
+                          const int64_t *w, int64_t *ps, int64_t *x1, int64_t *x2,
+                          int32_t *scratch, int64_t *kid_off) {
+    int32_t *vis = scratch, *fin = scratch + n, *kids = scratch + 2 * n, *stack = scratch + 3 * n,
+            *it = scratch + 4 * n;   /* it[a]: next child of a to visit */
+    /* 1. path support, walking every node's tree path */
+    for (int64_t a = 0; a < n; ++a) ps[a] = 0;
+    for (int64_t u = 0; u < n; ++u)
+        for (int32_t a = (int32_t)u; a != root; a = next[a]) ps[a] += w[u];
+    /* 2. DFS from the root over child lists (children in ascending id) */
+    for (int64_t i = 0; i <= n; ++i) kid_off[i] = 0;
+    for (int64_t u = 0; u < n; ++u)
+        if (u != root) kid_off[next[u] + 1] += 1;
+    for (int64_t i = 0; i < n; ++i) kid_off[i + 1] += kid_off[i];
+    for (int64_t i = 0; i < n; ++i) stack[i] = 0;           /* fill cursors */
+    for (int64_t u = 0; u < n; ++u)
+        if (u != root) kids[kid_off[next[u]] + stack[next[u]]++] = (int32_t)u;
+    int32_t clock = 0, top = 0;
+    /* iterative DFS: stack holds nodes; vis set on entry, fin on exit */
+    for (int64_t i = 0; i < n; ++i) { vis[i] = -1; fin[i] = -1; }
+    for (int64_t i = 0; i < n; ++i) it[i] = 0;
+    stack[top++] = root;
+    vis[root] = clock++;
+    while (top > 0) {
+        int32_t a = stack[top - 1];
+        if (kid_off[a] + it[a] < kid_off[a + 1]) {
+            int32_t c = kids[kid_off[a] + it[a]++];
+            vis[c] = clock++;
+            stack[top++] = c;
+        } else {
+            fin[a] = clock++;
+            --top;
+        }
+    }
+    /* 3. flows along the BFS path of every node */
+    for (int64_t u = 0; u < n; ++u) {
+        int64_t s1 = 0, s2 = 0;
+        for (int32_t e1 = (int32_t)u; e1 != root; e1 = bfs_par[e1]) {
+            int32_t e2 = bfs_par[e1];
+            if (next[e1] == e2 && vis[e1] <= vis[u] && fin[u] <= fin[e1]) {
+                s1 += 1;
+                s2 += ps[e1];
+            }
+            if (e2 != root && next[e2] == e1 && vis[e2] <= vis[u] && fin[u] <= fin[e2]) {
+                s1 -= 1;
+                s2 -= ps[e2];
+            }
+        }
+        x1[u] = s1;
+        x2[u] = s2;
+    }
+}
+
+/*
+ * SpanTree estimators over Wilson samples [sample_begin, sample_begin +
+ * n_samples) (the same trees as oracle_wilson draws for these indices):
+ *   kind 1 (Alg. 1): X1[u] += x1[u], X2[u] += x2[u] with w = 1 ([n] each);
+ *   kind 2 (Alg. 3): per sample, s1[s] = sum_u d_u x1[u] and
+ *                    s2[s] = sum_u d_u x2[u] with w = d ([n_samples] each).
+ * Returns 0, -1 on allocation failure, -2 if the graph is not connected.
+ */
+int32_t oracle_spantree(int64_t n, const int64_t *rp, const int32_t *col, int32_t root,
+                        uint64_t seed, uint32_t stream, uint64_t qid,
+                        int64_t sample_begin, int64_t n_samples, int32_t kind,
+                        int64_t *X1, int64_t *X2, int64_t *s1, int64_t *s2, int32_t n_threads) {
+    int32_t *bfs_par = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *wt = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!bfs_par || !wt) { free(bfs_par); free(wt); return -1; }
+    if (oracle_bfs_tree(n, rp, col, root, bfs_par) != n) { free(bfs_par); free(wt); return -2; }
+    for (int64_t u = 0; u < n; ++u) wt[u] = kind == 2 ? rp[u + 1] - rp[u] : 1;
+    if (kind == 1) for (int64_t u = 0; u < n; ++u) { X1[u] = 0; X2[u] = 0; }
+    int32_t status = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        uint8_t *intree = (uint8_t *)malloc((size_t)n);
+        int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int32_t *draws = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        int64_t *ps = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        int64_t *x1 = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        int64_t *x2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        int32_t *scr = (int32_t *)malloc(sizeof(int32_t) * 5 * (size_t)n);
+        int64_t *koff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        int64_t *A1 = kind == 1 ? (int64_t *)calloc((size_t)n, sizeof(int64_t)) : NULL;
+        int64_t *A2 = kind == 1 ? (int64_t *)calloc((size_t)n, sizeof(int64_t)) : NULL;
+        if (!intree || !next || !draws || !ps || !x1 || !x2 || !scr || !koff || (kind == 1 && (!A1 || !A2))) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            status = -1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+            for (int64_t s = 0; s < n_samples; ++s) {
+                draw_ctx dc;
+                memset(&dc, 0, sizeof dc);
+                dc.rp = rp; dc.col = col; dc.k0 = seed; dc.k1 = make_key1(stream, root);
+                dc.c0 = (uint64_t)(sample_begin + s); dc.qid = qid;
+                wilson_sample(n, root, &dc, NULL, 0, intree, next, draws, NULL, 0, NULL);
+                oracle_spantree_tree(n, next, root, bfs_par, wt, ps, x1, x2, scr, koff);
+                if (kind == 1) {
+                    for (int64_t u = 0; u < n; ++u) { A1[u] += x1[u]; A2[u] += x2[u]; }
+                } else {
+                    int64_t a = 0, b = 0;
+                    for (int64_t u = 0; u < n; ++u) { a += wt[u] * x1[u]; b += wt[u] * x2[u]; }
+                    s1[s] = a;
+                    s2[s] = b;
+                }
+            }
+            if (kind == 1) {
+#ifdef _OPENMP
+#pragma omp critical(oracle_spantree)
+#endif
+                for (int64_t u = 0; u < n; ++u) { X1[u] += A1[u]; X2[u] += A2[u]; }
+            }
+        }
+        free(intree); free(next); free(draws); free(ps); free(x1); free(x2); free(scr); free(koff);
+        free(A1); free(A2);
+    }
+    free(bfs_par); free(wt);
+    return status;
+}
