@@ -253,6 +253,47 @@ void lap_batch_free(lap_batch *b);
 int lap_landmark_traces(lap_graph *g, const int32_t *roots, int32_t n_roots, int64_t omega, uint64_t seed,
                         double *trace, double *trace_se, void *hip_stream);
 
+/* ---------------------------------------------------------------- SpanTree */
+
+/*
+ * lap_spantree -- the per-tree sums of the SpanTree estimators (Alg. 1 for
+ * diag(L^dagger) and closeness, Alg. 3 for Kemeny's constant) over the
+ * Wilson trees of samples [sample_begin, sample_begin + n_samples): the same
+ * trees lap_sample_forests draws for these arguments.  With T a sampled tree
+ * rooted at v and the BFS path of u towards v (a BFS tree from v, neighbours
+ * in ascending order), every edge (e1, e2) of that path which is a tree edge
+ * lying on u's own tree path (its lower end an ancestor-or-self of u, by DFS
+ * intervals) contributes the flow it carries in the direction e1 -> e2
+ * (Sec. 4.1 and Sec. 5.2; the containment test as printed is reversed, see
+ * the design notes):
+ *   x1(u)  +1 / -1            (unit current entering at u, leaving at v);
+ *   x2(u)  +/- |subtree(lower end)|            (1/n entering at every node,
+ *          in units of 1/n);
+ *   x2'(u) +/- degree sum of the subtree        (d_w/2m entering at every w,
+ *          in units of 1/2m).
+ * Outputs (int64; host memory unless a->want has LAP_OUT_DEVICE; any NULL):
+ *   X1, X2 [B][n]      per block b of samples (i*B/n_total == b), the sums
+ *                      of x1(u) and x2(u);
+ *   s1, s2 [n_samples] per sample, sum_u d_u x1(u) and sum_u d_u x2'(u).
+ * Arguments as for lap_sample_forests (mode, pool, group, schedule, seed,
+ * stream, qid); want bits other than LAP_OUT_DEVICE are ignored.  The BFS
+ * tree is computed on the host once per root.  Scratch: 36 bytes per node
+ * per tree in flight (at most 48 GiB).  LAP_ENOTCONN for a disconnected graph.
+ */
+int lap_spantree(lap_graph *g, const lap_sample_args *a, int64_t *X1, int64_t *X2, int64_t *s1, int64_t *s2,
+                 void *hip_stream);
+
+/*
+ * lap_spantree_estimate -- FP64 SpanTree estimates of a whole sample set
+ * (sample_begin 0, n_total = n_samples): diag [n] = x1(u) - 2 x2(u) +
+ * (1/n) sum_w x2(w) with x1 = X1/omega and x2 = X2/(n omega) (Alg. 1, last
+ * loop); diag_se [n] by batch means over the B blocks; closeness [n] =
+ * (n-1)/(Tr + n diag(u)); kemeny = mean over samples of s1 - s2/2m (Alg. 3)
+ * and kemeny_se.  Any output may be NULL; host or device as above.
+ */
+int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, double *diag, double *diag_se, double *closeness,
+                          double *kemeny, double *kemeny_se, void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /*
@@ -312,13 +353,13 @@ typedef struct {
     uint32_t stream;
     int64_t global_samples;  /* samples for the cached global terms; 0 = 256 */
     int64_t arena_bytes;     /* device memory for query results; 0 = 64 MiB */
-    int32_t launches;        /* launches in flight (streams); 0 = 2 */
+    int32_t launches;        /* launches in flight (streams); 0 = 3 */
     int32_t waves;           /* wavefronts (Wilson state slots) per launch; 0 = 4 per CU */
     int32_t items_per_launch;/* 0 = 4096 */
     int32_t wilson_chunk;    /* Wilson samples per work item; 0 = 1 */
     double timeout_s;        /* kernel time limit; 0 = 300 s */
     int32_t wilson_group;    /* wavefronts per Wilson sample in Wilson launches: 1 = wave form,
-                                2, 4 or 8 = workgroup form; 0 = 8 on graphs of >= 2^16 nodes, else 1 */
+                                2, 4 or 8 = workgroup form; 0 = 4 on graphs of >= 2^16 nodes, else 1 */
 } lap_server_config;
 
 /* Compute the cached global terms (lap_sample_forests with qid
@@ -348,8 +389,8 @@ const char *lap_last_error(void);
 /* Kernel timing: when enabled, every kernel launch of the library is
  * bracketed by HIP events on the stream it runs on; lap_prof_read returns
  * the accumulated milliseconds and launch count for a kernel name
- * ("wilson_wave", "wilson_lane", "wilson_group", "absorbed", "assemble",
- * "batch", "batch_assemble").  Returns
+ * ("wilson_wave", "wilson_lane", "wilson_group", "spantree", "absorbed",
+ * "assemble", "batch", "batch_assemble").  Returns
  * LAP_EINVAL for an unknown name. */
 int lap_prof_enable(int on);
 int lap_prof_reset(void);

@@ -133,3 +133,14 @@ def spantree_kemeny(s1, s2, two_m):
     est = math.fsum(z.tolist()) / omega
     se = float(z.std(ddof=1) / math.sqrt(omega)) if omega > 1 else float("nan")
     return est, se
+
+
+def spantree_diag_blocks(X1b, X2b, omega, n):
+    """Alg. 1 estimate from per-block sums ([B][n]) and its batch-means
+    standard error (blocks of floor(i*B/omega) samples)."""
+    B = X1b.shape[0]
+    sizes = block_sizes(omega, B)
+    est = np.stack([spantree_diag(X1b[b], X2b[b], int(sizes[b]), n) for b in range(B)])
+    full = spantree_diag(X1b.sum(0), X2b.sum(0), omega, n)
+    se = est.std(axis=0, ddof=1) / math.sqrt(B) if B > 1 else np.full(n, np.nan)
+    return full, se

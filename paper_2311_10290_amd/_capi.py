@@ -19,7 +19,7 @@ EXPORTS = [
     "lap_last_error", "lap_prof_enable", "lap_prof_reset", "lap_prof_read", "lap_last_stats",
     "lap_bench_gather",
     "lap_batch_create", "lap_batch_job_info", "lap_batch_run", "lap_batch_autotune", "lap_batch_result",
-    "lap_batch_stats", "lap_batch_free", "lap_landmark_traces",
+    "lap_batch_stats", "lap_batch_free", "lap_landmark_traces", "lap_spantree", "lap_spantree_estimate",
     "lap_server_create", "lap_server_submit", "lap_server_step", "lap_server_poll", "lap_server_pending",
     "lap_server_globals", "lap_server_free",
 ]
@@ -116,6 +116,8 @@ def declare(lib):
         "lap_batch_stats": ([P, P, P, P], i32),
         "lap_batch_free": ([P], None),
         "lap_landmark_traces": ([P, P, i32, i64, u64, P, P, P], i32),
+        "lap_spantree": ([P, ctypes.POINTER(SampleArgs), P, P, P, P, P], i32),
+        "lap_spantree_estimate": ([P, ctypes.POINTER(SampleArgs), P, P, P, P, P, P], i32),
         "lap_server_create": ([P, ctypes.POINTER(ServerConfig), P, P], i32),
         "lap_server_submit": ([P, ctypes.POINTER(Query)], i32),
         "lap_server_step": ([P, i32], i32),

@@ -176,6 +176,28 @@ class Graph:
         _check(load_library().lap_estimate(self._h, ctypes.byref(a), ctypes.byref(e), _stream(stream)))
         return res
 
+    def spantree(self, omega, seed, root=-1, *, B=1, sample_begin=0, n_total=0, mode=0, pool=0, group=0,
+                 stream_id=0, qid=0, timeout_s=0.0, schedule=0, stream=None):
+        """SpanTree per-tree sums (lap_spantree): X1, X2 [B][n]; s1, s2 [omega]."""
+        a = self._args(omega, seed, root, 0, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s,
+                       schedule, group)
+        out = dict(X1=np.zeros((B, self.n), np.int64), X2=np.zeros((B, self.n), np.int64),
+                   s1=np.zeros(omega, np.int64), s2=np.zeros(omega, np.int64))
+        _check(load_library().lap_spantree(self._h, ctypes.byref(a), _ptr(out["X1"]), _ptr(out["X2"]),
+                                           _ptr(out["s1"]), _ptr(out["s2"]), _stream(stream)))
+        return out
+
+    def spantree_estimate(self, omega, seed, root=-1, *, B=64, mode=0, pool=0, group=0, stream_id=0, qid=0,
+                          timeout_s=0.0, stream=None):
+        """SpanTree FP64 estimates (lap_spantree_estimate)."""
+        a = self._args(omega, seed, root, 0, B, 0, 0, mode, pool, stream_id, qid, timeout_s, group=group)
+        res = dict(diag=np.zeros(self.n), diag_se=np.zeros(self.n), closeness=np.zeros(self.n),
+                   kemeny=np.zeros(1), kemeny_se=np.zeros(1))
+        _check(load_library().lap_spantree_estimate(self._h, ctypes.byref(a), *[_ptr(res[k]) for k in
+                                                    ("diag", "diag_se", "closeness", "kemeny", "kemeny_se")],
+                                                    _stream(stream)))
+        return res
+
     def landmark_traces(self, roots, omega, seed, stream=None):
         """Tr((I-P_v)^{-1}) estimate (mean Wilson draws) and its SE for each root."""
         roots = np.ascontiguousarray(roots, np.int32)

@@ -330,7 +330,7 @@ int finish(lap_graph *g, hipStream_t s, Timer &tm) {
         g->state_dirty = true;
         switch (e.code) {
             case kErrDrawOverflow:
-                return fail(LAP_ERANGE, "more than 2^24-1 draws at node " + std::to_string(e.detail) +
+                return fail(LAP_ERANGE, "more than 2^21-1 draws at node " + std::to_string(e.detail) +
                                             " in one sample");
             case kErrTimeout:
                 return fail(LAP_ERANGE, "kernel time limit exceeded");
@@ -473,6 +473,143 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
         (rc = copy_out(out->rw_betweenness, d_rwb, sizeof(double) * n, s)))
         return rc;
     HIP_TRY(hipStreamSynchronize(s));
+    return LAP_OK;
+}
+
+// ---------------------------------------------------------------- SpanTree
+namespace {
+
+// Wilson trees for the samples of r, `slots` at a time, each round followed by
+// the SpanTree pass over the trees in the state slots.  Fills g->span_x
+// (X1 then X2, [B][n] each) and g->span_s (s1 then s2, [omega] each).
+int span_run(lap_graph *g, const lap_sample_args *a, const Resolved &r, hipStream_t s, Timer &tm) {
+    const int64_t n = g->csr.n;
+    if (g->bfs_root != r.root) {
+        std::vector<int32_t> par;
+        if (bfs_parents(g->csr, r.root, par) != n) return fail(LAP_ENOTCONN, "graph is not connected");
+        if (g->bfs_par.ensure(sizeof(int32_t) * (size_t)n)) return fail(LAP_ENOMEM, "cannot allocate BFS tree");
+        HIP_TRY(hipMemcpyAsync(g->bfs_par.ptr, par.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));   // par lives on this stack frame
+        g->bfs_root = r.root;
+    }
+    // trees per round: the sampling slots, within 48 GiB of tree scratch
+    const int64_t per_tree = (8 + 4 * kSpanInt32PerNode) * std::max<int64_t>(n, 1);
+    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(r.slots, ((int64_t)48 << 30) / per_tree));
+    if (g->span64.ensure(sizeof(int64_t) * (size_t)slots * n) ||
+        g->span32.ensure(sizeof(int32_t) * (size_t)kSpanInt32PerNode * slots * n) ||
+        g->span_x.ensure(sizeof(uint64_t) * 2 * (size_t)r.B * n) ||
+        g->span_s.ensure(sizeof(int64_t) * 2 * (size_t)r.omega))
+        return fail(LAP_ENOMEM, "cannot allocate SpanTree workspace");
+    HIP_TRY(launch_fill_u64(g->span_x.as<uint64_t>(), 0ull, 2 * (int64_t)r.B * n, s));
+    int64_t acc[kNumStats] = {0};
+    for (int64_t done = 0; done < r.omega; done += slots) {
+        Resolved rr = r;
+        rr.omega = std::min(slots, r.omega - done);
+        rr.begin = r.begin + done;
+        rr.slots = rr.omega;
+        rr.wilson = true;
+        rr.y2u = rr.y2p = false;
+        RunOut o;
+        int rc = run_sampling(g, rr, a, 0, nullptr, false, false, o, s, tm);
+        if (rc != LAP_OK) return rc;
+        SpanParams p;
+        std::memset(&p, 0, sizeof p);
+        p.n = n;
+        p.nbr = g->nbr.as<uint64_t>();
+        p.root = r.root;
+        p.state = g->state.as<uint64_t>();
+        p.n_trees = rr.omega;
+        p.sample_begin = rr.begin;
+        p.n_total = r.total;
+        p.n_blocks = r.B;
+        p.bfs_par = g->bfs_par.as<int32_t>();
+        p.scratch64 = g->span64.as<int64_t>();
+        p.scratch32 = g->span32.as<int32_t>();
+        p.X1 = g->span_x.as<unsigned long long>();
+        p.X2 = p.X1 + (int64_t)r.B * n;
+        p.s1 = g->span_s.as<long long>() + done;
+        p.s2 = g->span_s.as<long long>() + r.omega + done;
+        p.err = g->err.as<DevErr>();
+        tm.begin("spantree", s);
+        HIP_TRY(launch_spantree(p, s));
+        tm.end(s);
+        rc = finish(g, s, tm);
+        if (rc != LAP_OK) return rc;
+        for (int i = 0; i < kNumStats; ++i) acc[i] += g->last_stats[i];
+    }
+    for (int i = 0; i < kNumStats; ++i) g->last_stats[i] = acc[i];
+    return LAP_OK;
+}
+
+}  // namespace
+
+extern "C" int lap_spantree(lap_graph *g, const lap_sample_args *a, int64_t *X1, int64_t *X2, int64_t *s1,
+                            int64_t *s2, void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    Resolved r;
+    int rc = resolve_args(g, a, 0, nullptr, r);
+    if (rc != LAP_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    Timer tm;
+    if ((rc = span_run(g, a, r, s, tm)) != LAP_OK) return rc;
+    const int64_t n = g->csr.n;
+    const size_t bn = sizeof(int64_t) * (size_t)r.B * n;
+    const int64_t *x = g->span_x.as<int64_t>(), *ps = g->span_s.as<int64_t>();
+    if ((rc = copy_out(X1, x, bn, s)) || (rc = copy_out(X2, x + (int64_t)r.B * n, bn, s)) ||
+        (rc = copy_out(s1, ps, sizeof(int64_t) * r.omega, s)) ||
+        (rc = copy_out(s2, ps + r.omega, sizeof(int64_t) * r.omega, s)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return LAP_OK;
+}
+
+extern "C" int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, double *diag, double *diag_se,
+                                     double *closeness, double *kemeny, double *kemeny_se, void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    Resolved r;
+    int rc = resolve_args(g, a, 0, nullptr, r);
+    if (rc != LAP_OK) return rc;
+    if (r.begin != 0 || r.total != r.omega)
+        return fail(LAP_EINVAL, "a SpanTree estimate runs a whole sample set: sample_begin = 0, n_total = n_samples");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Timer tm;
+    if ((rc = span_run(g, a, r, s, tm)) != LAP_OK) return rc;
+    const int64_t n = g->csr.n;
+    std::vector<int64_t> bn((size_t)r.B);
+    for (int32_t b = 0; b < r.B; ++b)
+        bn[b] = ((int64_t)(b + 1) * r.total + r.B - 1) / r.B - ((int64_t)b * r.total + r.B - 1) / r.B;
+    // device outputs: diag, diag_se, closeness [n]; trace, kemeny, kemeny_se; block sizes and sums
+    if (g->est_out.ensure(sizeof(double) * (3 * (size_t)n + 3) + 2 * sizeof(int64_t) * (size_t)r.B))
+        return fail(LAP_ENOMEM, "cannot allocate estimates");
+    double *d = g->est_out.as<double>();
+    int64_t *blk = (int64_t *)(d + 3 * n + 3);
+    HIP_TRY(hipMemcpyAsync(blk, bn.data(), sizeof(int64_t) * r.B, hipMemcpyHostToDevice, s));
+    SpanAsmParams p;
+    std::memset(&p, 0, sizeof p);
+    p.n = n;
+    p.omega = r.omega;
+    p.two_m = g->csr.rp[n];
+    p.B = r.B;
+    p.X1 = g->span_x.as<unsigned long long>();
+    p.X2 = p.X1 + (int64_t)r.B * n;
+    p.blk_n = blk;
+    p.blk_sum = (long long *)(blk + r.B);
+    p.s1 = g->span_s.as<long long>();
+    p.s2 = p.s1 + r.omega;
+    const bool want_diag = diag || diag_se || closeness;
+    p.diag = want_diag ? d : nullptr;
+    p.diag_se = diag_se ? d + n : nullptr;
+    p.closeness = closeness ? d + 2 * n : nullptr;
+    p.trace = d + 3 * n;
+    p.kemeny = (kemeny || kemeny_se) ? d + 3 * n + 1 : nullptr;
+    p.kemeny_se = kemeny_se ? d + 3 * n + 2 : nullptr;
+    HIP_TRY(launch_span_assemble(p, s));
+    if ((rc = copy_out(diag, d, sizeof(double) * n, s)) || (rc = copy_out(diag_se, d + n, sizeof(double) * n, s)) ||
+        (rc = copy_out(closeness, d + 2 * n, sizeof(double) * n, s)) ||
+        (rc = copy_out(kemeny, d + 3 * n + 1, sizeof(double), s)) ||
+        (rc = copy_out(kemeny_se, d + 3 * n + 2, sizeof(double), s)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(s));   // bn lives on this stack frame
     return LAP_OK;
 }
 

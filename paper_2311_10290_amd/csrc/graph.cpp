@@ -134,3 +134,30 @@ int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t
 }
 
 }  // namespace lap
+
+namespace lap {
+
+int64_t bfs_parents(const HostCSR &g, int32_t root, std::vector<int32_t> &par) {
+    const int64_t n = g.n;
+    par.assign((size_t)n, -1);
+    if (n == 0) return 0;
+    std::vector<int32_t> queue;
+    queue.reserve((size_t)n);
+    std::vector<uint8_t> seen((size_t)n, 0);
+    queue.push_back(root);
+    seen[root] = 1;
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const int32_t a = queue[h];
+        for (int64_t j = g.rp[a]; j < g.rp[a + 1]; ++j) {
+            const int32_t b = g.col[j];
+            if (!seen[b]) {
+                seen[b] = 1;
+                par[b] = a;
+                queue.push_back(b);
+            }
+        }
+    }
+    return (int64_t)queue.size();
+}
+
+}  // namespace lap

@@ -214,4 +214,33 @@ struct ServeParams {
     uint64_t deadline;
 };
 
+// SpanTree pass over the trees left in the Wilson state slots (spantree.hip)
+constexpr int64_t kSpanInt32PerNode = 7;   // scratch per node per tree: 7 int32 + 1 int64
+
+struct SpanParams {
+    int64_t n;
+    const uint64_t *nbr;
+    int32_t root;
+    const uint64_t *state;         // [slots][n]: slot s holds the tree of sample sample_begin + s
+    int64_t n_trees;
+    int64_t sample_begin, n_total;
+    int32_t n_blocks;
+    const int32_t *bfs_par;        // [n] BFS parents from the root (-1 at the root)
+    int64_t *scratch64;            // [n_trees][n]
+    int32_t *scratch32;            // [n_trees][7][n]
+    unsigned long long *X1, *X2;   // [B][n] unit-flow and path-support sums, or null
+    long long *s1, *s2;            // [n_trees] Kemeny terms of this launch's samples, or null
+    DevErr *err;
+};
+
+struct SpanAsmParams {
+    int64_t n, omega, two_m;
+    int32_t B;
+    const unsigned long long *X1, *X2;   // [B][n]
+    const int64_t *blk_n;                // [B] samples per block
+    long long *blk_sum;                  // [B] scratch
+    const long long *s1, *s2;            // [omega]
+    double *diag, *diag_se, *closeness, *trace, *kemeny, *kemeny_se;   // any may be null (diag needed for the rest)
+};
+
 }  // namespace lap

@@ -22,6 +22,10 @@ struct HostCSR {
 int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst, bool keep_lcc,
                    HostCSR &out, std::string &err);
 
+// BFS tree of the CSR from root, neighbours in ascending order: par[u] is u's
+// parent, -1 at the root.  Returns the number of nodes reached.
+int64_t bfs_parents(const HostCSR &g, int32_t root, std::vector<int32_t> &par);
+
 // Set the thread's error text and return code.
 int fail(int code, const std::string &msg);
 
@@ -76,12 +80,16 @@ struct lap_graph {
     bool state_dirty = false;
     lap::DevBuf y1, y2, y1s, len_u, len_p, keep_next, keep_draws, err, stats;
     lap::DevBuf asm_partial, asm_sums, asm_trace, est_out, blkcount;
+    // SpanTree workspace: BFS parents for bfs_root, per-tree scratch, sums
+    int32_t bfs_root = -1;
+    lap::DevBuf bfs_par, span64, span32, span_x, span_s;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t last_stats[lap::kNumStats] = {0};
     ~lap_graph() {
         lap::DevBuf *bufs[] = {&rp, &nbr, &col, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
-                          &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount};
+                          &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount,
+                          &bfs_par, &span64, &span32, &span_x, &span_s};
         for (lap::DevBuf *b : bufs) b->release();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);

@@ -338,12 +338,12 @@ extern "C" int lap_server_create(lap_graph *g, const lap_server_config *cfg, voi
     if (c.root < 0) c.root = g->max_deg_node;
     if (c.global_samples == 0) c.global_samples = 256;
     if (c.arena_bytes == 0) c.arena_bytes = (int64_t)64 << 20;
-    if (c.launches == 0) c.launches = 2;
+    if (c.launches == 0) c.launches = 3;
     if (c.waves == 0) c.waves = 4 * g->n_cu;
     if (c.items_per_launch == 0) c.items_per_launch = 4096;
     if (c.wilson_chunk == 0) c.wilson_chunk = 1;
     if (c.timeout_s <= 0) c.timeout_s = 300.0;
-    if (c.wilson_group == 0) c.wilson_group = s->n >= (1 << 16) ? 8 : 1;
+    if (c.wilson_group == 0) c.wilson_group = s->n >= (1 << 16) ? 4 : 1;
     s->k1 = ((uint64_t)c.stream << 32) | (uint64_t)(uint32_t)c.root;
     s->deadline = (uint64_t)(c.timeout_s * g->clock_khz * 1000.0);
     // cached global terms: Tr(L_v^{-1}) and 1^T L_v^{-1} 1 from one Wilson +

@@ -1,0 +1,336 @@
+// SpanTree estimators (Alg. 1 for diag(L^dagger) and closeness, Alg. 3 for
+// Kemeny's constant) on the spanning trees the Wilson kernels leave in their
+// state slots: after a launch with at most one sample per slot, slot s holds
+// sample s's tree as the next fields of its state words.
+//
+// One workgroup processes one tree (n nodes) in six steps over the slot's
+// scratch arrays, with a barrier between steps:
+//   1. child counts;
+//   2. subtree sizes sz and degree sums psd, bottom-up: every leaf climbs
+//      towards v, and at each parent the last child to arrive carries the
+//      climb on (so every node is finished exactly once);
+//   3. sibling offsets: each child reserves a range of its parent's
+//      subtree (any order of siblings gives a valid pre-order);
+//   4. pre-order numbers by pointer jumping: pre[u] = sum over u's tree path
+//      (without v) of 1 + offset, so u's subtree is [pre[u], pre[u] + sz[u]);
+//   5. the BFS-path pass: for every u, each edge (e1, e2) of u's BFS path
+//      that is a tree edge on u's tree path adds its flow in the direction
+//      e1 -> e2: +1 / -1 to x1(u), +/- the path support (sz for unit weights,
+//      psd for degree weights) to x2(u) (Alg. 1 and Alg. 3, inner loops);
+//   6. the sample's sums: x1(u), x2(u) (sz) are added to the per-node block
+//      counts, sum_u d_u x1(u) and sum_u d_u x2(u) (psd) to the per-sample
+//      Kemeny terms.
+// Path support is kept in integer units (1/n for Alg. 1, 1/2m for Alg. 3),
+// so every output is an exact integer and independent of thread timing.
+#include "lap_device.h"
+#include "lap_launch.h"
+
+namespace lap {
+
+constexpr int kSpanThreads = 256;
+constexpr int kSpanWave = 64;
+
+struct SpanScratch {
+    int64_t *psd;
+    int32_t *cnt, *acc, *sz, *s0, *s1, *u0, *u1;
+};
+
+__device__ __forceinline__ SpanScratch span_scratch(const SpanParams &p, int64_t slot) {
+    SpanScratch s;
+    s.psd = p.scratch64 + slot * p.n;
+    int32_t *b = p.scratch32 + slot * kSpanInt32PerNode * p.n;
+    s.cnt = b;
+    s.acc = b + p.n;
+    s.sz = b + 2 * p.n;
+    s.s0 = b + 3 * p.n;
+    s.s1 = b + 4 * p.n;
+    s.u0 = b + 5 * p.n;
+    s.u1 = b + 6 * p.n;
+    return s;
+}
+
+__device__ __forceinline__ int64_t span_block(int64_t sample, int32_t B, int64_t n_total) {
+    return (sample * (int64_t)B) / n_total;
+}
+
+__device__ __forceinline__ int64_t ld_acq64(const int64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_acq32(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// all threads of the workgroup: barrier, then drop stale L1 lines of data
+// other threads changed with atomics
+__device__ __forceinline__ void span_sync() {
+    __syncthreads();
+    __threadfence();
+}
+
+__global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
+    __shared__ int32_t flag, bad;
+    __shared__ long long red1[kSpanThreads / kSpanWave], red2[kSpanThreads / kSpanWave];
+    const int tid = (int)threadIdx.x;
+    const int64_t slot = blockIdx.x;
+    if (slot >= p.n_trees) return;
+    const int64_t n = p.n;
+    const int32_t root = p.root;
+    const uint64_t *st = p.state + slot * n;
+    SpanScratch s = span_scratch(p, slot);
+    const int64_t sample = p.sample_begin + slot;
+
+    // 1. initial values and child counts; every parent must be a node
+    if (tid == 0) bad = 0;
+    for (int64_t a = tid; a < n; a += kSpanThreads) {
+        s.cnt[a] = 0;
+        s.acc[a] = 0;
+        s.sz[a] = 1;
+        s.psd[a] = (int64_t)nbr_deg(p.nbr[a]);
+    }
+    span_sync();
+    for (int64_t u = tid; u < n; u += kSpanThreads)
+        if (u != root) {
+            const int32_t nx = st_next(st[u]);
+            if (nx < 0 || nx >= n || nx == u) {
+                raise_err(p.err, kErrInconsistent, -10);
+                bad = 1;
+            } else {
+                atomicAdd(&s.cnt[nx], 1);
+            }
+        }
+    span_sync();
+    if (bad) return;   // the same LDS value for every thread after the barrier
+    // the leaves, fixed before any count is consumed
+    for (int64_t u = tid; u < n; u += kSpanThreads) s.s0[u] = ld_acq32(&s.cnt[u]);
+    span_sync();
+
+    // 2. bottom-up sums: leaves climb; the last child at a parent continues
+    for (int64_t u = tid; u < n; u += kSpanThreads) {
+        if (u == root || s.s0[u] != 0) continue;
+        int32_t a = (int32_t)u;
+        int32_t za = 1;
+        int64_t pa = (int64_t)nbr_deg(p.nbr[a]);
+        for (int64_t guard = 0; guard < n; ++guard) {
+            const int32_t par = st_next(st[a]);
+            atomicAdd(&s.sz[par], za);
+            atomicAdd((unsigned long long *)&s.psd[par], (unsigned long long)pa);
+            const int32_t before =
+                __hip_atomic_fetch_add(&s.cnt[par], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (before != 1 || par == root) break;
+            a = par;
+            za = ld_acq32(&s.sz[a]);
+            pa = ld_acq64(&s.psd[a]);
+        }
+    }
+    span_sync();
+
+    // 3. sibling offsets (stored in cnt, now all zero)
+    for (int64_t u = tid; u < n; u += kSpanThreads)
+        if (u != root) s.cnt[u] = atomicAdd(&s.acc[st_next(st[u])], ld_acq32(&s.sz[u]));
+    span_sync();
+
+    // 4. pre-order numbers: S[u] = 1 + offset, U[u] = parent (v: 0 and v),
+    // doubled until every U is v; S then holds pre[u]
+    int32_t *S0 = s.s0, *S1 = s.s1, *U0 = s.u0, *U1 = s.u1;
+    for (int64_t u = tid; u < n; u += kSpanThreads) {
+        S0[u] = (u == root) ? 0 : 1 + s.cnt[u];
+        U0[u] = (u == root) ? root : st_next(st[u]);
+    }
+    for (int round = 0; round < 40; ++round) {
+        if (tid == 0) flag = 0;
+        __syncthreads();
+        bool more = false;
+        for (int64_t u = tid; u < n; u += kSpanThreads) {
+            const int32_t up = U0[u];
+            S1[u] = S0[u] + S0[up];
+            const int32_t up2 = U0[up];
+            U1[u] = up2;
+            more |= (up2 != root);
+        }
+        if (more) flag = 1;
+        __syncthreads();
+        const int f = flag;
+        int32_t *t = S0;
+        S0 = S1;
+        S1 = t;
+        t = U0;
+        U0 = U1;
+        U1 = t;
+        __syncthreads();
+        if (!f) break;
+    }
+    const int32_t *pre = S0;
+
+    // 5. BFS-path pass, 6. sums
+    const int32_t *bp = p.bfs_par;
+    unsigned long long *X1 = p.X1 ? p.X1 + span_block(sample, p.n_blocks, p.n_total) * n : nullptr;
+    unsigned long long *X2 = p.X2 ? p.X2 + span_block(sample, p.n_blocks, p.n_total) * n : nullptr;
+    long long k1 = 0, k2 = 0;
+    for (int64_t u = tid; u < n; u += kSpanThreads) {
+        const int32_t pu = pre[u];
+        int64_t x1 = 0, x2 = 0, x2d = 0;
+        int32_t e1 = (int32_t)u;
+        for (int hop = 0; hop < n && e1 != root; ++hop) {
+            const int32_t e2 = bp[e1];
+            if (st_next(st[e1]) == e2) {
+                const int32_t lo = pre[e1], sz = s.sz[e1];
+                if (lo <= pu && pu < lo + sz) {
+                    x1 += 1;
+                    x2 += sz;
+                    x2d += s.psd[e1];
+                }
+            }
+            if (e2 != root && st_next(st[e2]) == e1) {
+                const int32_t lo = pre[e2], sz = s.sz[e2];
+                if (lo <= pu && pu < lo + sz) {
+                    x1 -= 1;
+                    x2 -= sz;
+                    x2d -= s.psd[e2];
+                }
+            }
+            e1 = e2;
+        }
+        if (X1 && x1) atomicAdd(&X1[u], (unsigned long long)x1);
+        if (X2 && x2) atomicAdd(&X2[u], (unsigned long long)x2);
+        const int64_t d = (int64_t)nbr_deg(p.nbr[u]);
+        k1 += d * x1;
+        k2 += d * x2d;
+    }
+    // workgroup sums of the Kemeny terms
+#pragma unroll
+    for (int off = kSpanWave / 2; off > 0; off >>= 1) {
+        k1 += __shfl_xor(k1, off, kSpanWave);
+        k2 += __shfl_xor(k2, off, kSpanWave);
+    }
+    if ((tid & (kSpanWave - 1)) == 0) {
+        red1[tid / kSpanWave] = k1;
+        red2[tid / kSpanWave] = k2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long a = 0, b = 0;
+        for (int w = 0; w < kSpanThreads / kSpanWave; ++w) {
+            a += red1[w];
+            b += red2[w];
+        }
+        if (p.s1) p.s1[slot] = a;
+        if (p.s2) p.s2[slot] = b;
+    }
+}
+
+// ------------------------------------------------------------------ assembly
+// One workgroup, fixed-order reductions.  Alg. 1's last loop per block b of
+// omega_b samples: est_b(u) = X1_b(u)/omega_b - 2 X2_b(u)/(n omega_b) +
+// sum_w X2_b(w)/(n^2 omega_b); the estimate uses the sums over all blocks,
+// the standard error the spread of the block estimates.  Closeness is
+// (n-1)/(Tr + n diag(u)).  Alg. 3: kappa = mean over samples of s1 - s2/2m.
+constexpr int kAsmThreads = 1024;
+
+__device__ double asm_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = kAsmThreads / 2; off > 0; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ long long asm_sum_ll(long long v, long long *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = kAsmThreads / 2; off > 0; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    const long long r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kAsmThreads) void span_assemble_kernel(SpanAsmParams p) {
+    __shared__ double shd[kAsmThreads];
+    __shared__ long long shl[kAsmThreads];
+    const int t = threadIdx.x;
+    const int64_t n = p.n;
+    const double nn = (double)n;
+    const long long *X1 = (const long long *)p.X1, *X2 = (const long long *)p.X2;
+    if (p.diag) {
+        // block sums of X2 (exact integers) and their total
+        long long tot = 0;
+        for (int32_t b = 0; b < p.B; ++b) {
+            long long acc = 0;
+            for (int64_t u = t; u < n; u += kAsmThreads) acc += X2[(int64_t)b * n + u];
+            const long long sb = asm_sum_ll(acc, shl);
+            if (t == 0) p.blk_sum[b] = sb;
+            tot += sb;
+        }
+        __syncthreads();
+        const double om = (double)p.omega;
+        double tr = 0.0;
+        for (int64_t u = t; u < n; u += kAsmThreads) {
+            long long x1 = 0, x2 = 0;
+            double bs = 0.0;
+            auto block_est = [&](int32_t b) {
+                const double ob = (double)p.blk_n[b];
+                return (double)X1[(int64_t)b * n + u] / ob - 2.0 * (double)X2[(int64_t)b * n + u] / (nn * ob) +
+                       (double)p.blk_sum[b] / (nn * nn * ob);
+            };
+            for (int32_t b = 0; b < p.B; ++b) {
+                x1 += X1[(int64_t)b * n + u];
+                x2 += X2[(int64_t)b * n + u];
+                bs += block_est(b);
+            }
+            const double d = (double)x1 / om - 2.0 * (double)x2 / (nn * om) + (double)tot / (nn * nn * om);
+            p.diag[u] = d;
+            if (p.diag_se) {
+                const double B = (double)p.B, mean = bs / B;
+                double q = 0.0;
+                for (int32_t b = 0; b < p.B; ++b) {
+                    const double e = block_est(b) - mean;
+                    q += e * e;
+                }
+                p.diag_se[u] = p.B > 1 ? sqrt(q / (B - 1.0)) / sqrt(B) : __builtin_nan("");
+            }
+            tr += d;
+        }
+        const double Tr = asm_sum(tr, shd);
+        if (p.closeness)
+            for (int64_t u = t; u < n; u += kAsmThreads) p.closeness[u] = n > 1 ? (nn - 1.0) / (Tr + nn * p.diag[u]) : 0.0;
+        if (t == 0 && p.trace) *p.trace = Tr;
+    }
+    if (p.kemeny) {
+        const double two_m = (double)p.two_m;
+        double acc = 0.0;
+        for (int64_t i = t; i < p.omega; i += kAsmThreads) acc += (double)p.s1[i] - (double)p.s2[i] / two_m;
+        const double mean = asm_sum(acc, shd) / (double)p.omega;
+        double sq = 0.0;
+        for (int64_t i = t; i < p.omega; i += kAsmThreads) {
+            const double z = (double)p.s1[i] - (double)p.s2[i] / two_m - mean;
+            sq += z * z;
+        }
+        const double SQ = asm_sum(sq, shd);
+        if (t == 0) {
+            *p.kemeny = n > 1 ? mean : 0.0;
+            if (p.kemeny_se)
+                *p.kemeny_se = p.omega > 1 ? sqrt(SQ / ((double)p.omega - 1.0)) / sqrt((double)p.omega)
+                                           : __builtin_nan("");
+        }
+    }
+}
+
+hipError_t launch_span_assemble(const SpanAsmParams &p, hipStream_t s) {
+    hipLaunchKernelGGL(span_assemble_kernel, dim3(1), dim3(kAsmThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_spantree(const SpanParams &p, hipStream_t s) {
+    hipLaunchKernelGGL(spantree_kernel, dim3((unsigned)p.n_trees), dim3(kSpanThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace lap
