@@ -189,6 +189,31 @@ def _replay(lap, srv, qs, qid0):
     return lat, wall, bad
 
 
+def bench_spantree(lap, g, root, omega):
+    """SpanTree estimators (Alg. 1 + Alg. 3) on the mid workload: the same
+    Wilson trees as the plain LEWalk step, plus the per-tree pass; the
+    LEWalk estimate at the same omega is timed beside it."""
+    import torch
+    g.estimate(omega, 1, root, B=64)
+    t = time.perf_counter()
+    g.estimate(omega, 1, root, B=64)
+    lewalk_s = time.perf_counter() - t
+    g.spantree_estimate(omega, 1, root, B=64)
+    torch.cuda.synchronize()
+    lap.prof_reset()
+    lap.prof_enable(True)
+    t = time.perf_counter()
+    e = g.spantree_estimate(omega, 1, root, B=64)
+    dt = time.perf_counter() - t
+    lap.prof_enable(False)
+    ms_t, n_t = lap.prof_read("spantree")
+    ms_w, n_w = lap.prof_read("wilson_wave")
+    return {"workload": f"SpanTree closeness + Kemeny (Alg. 1, Alg. 3), same graph and trees, omega={omega}",
+            "s_per_step": dt, "trees_per_s": omega / dt, "spantree_kernel_ms": ms_t,
+            "wilson_kernel_ms": ms_w, "kemeny": float(e["kemeny"][0]), "kemeny_se": float(e["kemeny_se"][0]),
+            "lewalk_s_per_step_same_omega": lewalk_s, "spantree_over_lewalk_time": dt / lewalk_s}
+
+
 def _serial(lap, srv, qs, qid0):
     """The same queries one at a time: each is submitted when the previous
     one has completed (no batching across queries).  Returns the wall time."""
@@ -300,6 +325,7 @@ def main():
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-spantree", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
@@ -408,6 +434,9 @@ def main():
                          "peak_loads_per_s": peaks,
                          "frac_of_chase_peak_4GiB": achieved_loads / peaks["4GiB"]["chase"],
                          "state_bytes": 8 * g.n * min(omega, 4096)}
+    if not args.no_spantree:
+        log("spantree")
+        res["spantree"] = bench_spantree(lap, g, root, 1024)
     if not args.no_batch:
         res["batched"] = bench_batch(lap, gg, args.batch_jobs)
     if not args.no_serve:
