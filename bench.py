@@ -207,7 +207,7 @@ def bench_spantree(lap, g, root, omega):
     dt = time.perf_counter() - t
     lap.prof_enable(False)
     ms_t, n_t = lap.prof_read("spantree")
-    ms_w, n_w = lap.prof_read("wilson_wave")
+    ms_w = lap.prof_read("wilson_wave")[0] + lap.prof_read("wilson_group")[0]
     return {"workload": f"SpanTree closeness + Kemeny (Alg. 1, Alg. 3), same graph and trees, omega={omega}",
             "s_per_step": dt, "trees_per_s": omega / dt, "spantree_kernel_ms": ms_t,
             "wilson_kernel_ms": ms_w, "kemeny": float(e["kemeny"][0]), "kemeny_se": float(e["kemeny_se"][0]),

@@ -53,19 +53,24 @@ __device__ __forceinline__ int64_t span_block(int64_t sample, int32_t B, int64_t
     return (sample * (int64_t)B) / n_total;
 }
 
+// A tree is processed by one workgroup only, so every exchange below is
+// between threads of one workgroup (one CU): workgroup-scope atomics and
+// fences suffice and keep the L2 out of it.
 __device__ __forceinline__ int64_t ld_acq64(const int64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ int32_t ld_acq32(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void add32(int32_t *p, int32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void add64(int64_t *p, int64_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// all threads of the workgroup: barrier, then drop stale L1 lines of data
-// other threads changed with atomics
-__device__ __forceinline__ void span_sync() {
-    __syncthreads();
-    __threadfence();
-}
+// all threads of the workgroup: barrier with workgroup-scope release/acquire
+__device__ __forceinline__ void span_sync() { __syncthreads(); }
 
 __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
     __shared__ int32_t flag, bad;
@@ -95,7 +100,7 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
                 raise_err(p.err, kErrInconsistent, -10);
                 bad = 1;
             } else {
-                atomicAdd(&s.cnt[nx], 1);
+                add32(&s.cnt[nx], 1);
             }
         }
     span_sync();
@@ -112,10 +117,10 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
         int64_t pa = (int64_t)nbr_deg(p.nbr[a]);
         for (int64_t guard = 0; guard < n; ++guard) {
             const int32_t par = st_next(st[a]);
-            atomicAdd(&s.sz[par], za);
-            atomicAdd((unsigned long long *)&s.psd[par], (unsigned long long)pa);
+            add32(&s.sz[par], za);
+            add64(&s.psd[par], pa);
             const int32_t before =
-                __hip_atomic_fetch_add(&s.cnt[par], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&s.cnt[par], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (before != 1 || par == root) break;
             a = par;
             za = ld_acq32(&s.sz[a]);
@@ -126,7 +131,9 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
 
     // 3. sibling offsets (stored in cnt, now all zero)
     for (int64_t u = tid; u < n; u += kSpanThreads)
-        if (u != root) s.cnt[u] = atomicAdd(&s.acc[st_next(st[u])], ld_acq32(&s.sz[u]));
+        if (u != root)
+            s.cnt[u] = __hip_atomic_fetch_add(&s.acc[st_next(st[u])], ld_acq32(&s.sz[u]), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
     span_sync();
 
     // 4. pre-order numbers: S[u] = 1 + offset, U[u] = parent (v: 0 and v),
