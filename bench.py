@@ -214,6 +214,30 @@ def bench_spantree(lap, g, root, omega):
             "lewalk_s_per_step_same_omega": lewalk_s, "spantree_over_lewalk_time": dt / lewalk_s}
 
 
+def bench_landmark(lap, gg):
+    """Landmark study: Tr((I - P_v)^{-1}) for every node v of a
+    Barabasi-Albert graph n = 10,000, m = 5 as the candidate root, 32 Wilson
+    samples per root, all roots in one persistent launch."""
+    n, omega = 10_000, 32
+    src, dst = gg.barabasi_albert(n, 5, 0)
+    g = lap.Graph(n, src, dst)
+    roots = np.arange(n, dtype=np.int32)
+    g.landmark_traces(roots[:64], omega, 1)
+    t = time.perf_counter()
+    tr, se = g.landmark_traces(roots, omega, 1)
+    dt = time.perf_counter() - t
+    deg = np.diff(g.csr()[0])
+    order = np.argsort(tr)
+    res = {"workload": f"Barabasi-Albert n={n} m=5, every node as the root, {omega} trees per root, one launch",
+           "roots": n, "trees": n * omega, "s": dt, "trees_per_s": n * omega / dt,
+           "trace_over_n_max_degree_root": float(tr[int(np.argmax(deg))] / n),
+           "trace_over_n_median": float(np.median(tr) / n),
+           "trace_over_n_best": float(tr[order[0]] / n), "best_root_degree": int(deg[order[0]]),
+           "max_degree": int(deg.max())}
+    g.close()
+    return res
+
+
 def _serial(lap, srv, qs, qid0):
     """The same queries one at a time: each is submitted when the previous
     one has completed (no batching across queries).  Returns the wall time."""
@@ -326,6 +350,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-spantree", action="store_true")
+    ap.add_argument("--no-landmark", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
@@ -437,6 +462,9 @@ def main():
     if not args.no_spantree:
         log("spantree")
         res["spantree"] = bench_spantree(lap, g, root, 1024)
+    if not args.no_landmark:
+        log("landmark study")
+        res["landmark"] = bench_landmark(lap, gg)
     if not args.no_batch:
         res["batched"] = bench_batch(lap, gg, args.batch_jobs)
     if not args.no_serve:

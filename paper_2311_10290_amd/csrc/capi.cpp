@@ -578,11 +578,13 @@ extern "C" int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, dou
     std::vector<int64_t> bn((size_t)r.B);
     for (int32_t b = 0; b < r.B; ++b)
         bn[b] = ((int64_t)(b + 1) * r.total + r.B - 1) / r.B - ((int64_t)b * r.total + r.B - 1) / r.B;
-    // device outputs: diag, diag_se, closeness [n]; trace, kemeny, kemeny_se; block sizes and sums
-    if (g->est_out.ensure(sizeof(double) * (3 * (size_t)n + 3) + 2 * sizeof(int64_t) * (size_t)r.B))
+    // device outputs: diag, diag_se, closeness [n]; trace, kemeny, kemeny_se; partial traces;
+    // block sizes and sums
+    const int64_t parts = span_assemble_parts(n);
+    if (g->est_out.ensure(sizeof(double) * (3 * (size_t)n + 3 + (size_t)parts) + 2 * sizeof(int64_t) * (size_t)r.B))
         return fail(LAP_ENOMEM, "cannot allocate estimates");
     double *d = g->est_out.as<double>();
-    int64_t *blk = (int64_t *)(d + 3 * n + 3);
+    int64_t *blk = (int64_t *)(d + 3 * n + 3 + parts);
     HIP_TRY(hipMemcpyAsync(blk, bn.data(), sizeof(int64_t) * r.B, hipMemcpyHostToDevice, s));
     SpanAsmParams p;
     std::memset(&p, 0, sizeof p);
@@ -603,6 +605,8 @@ extern "C" int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, dou
     p.trace = d + 3 * n;
     p.kemeny = (kemeny || kemeny_se) ? d + 3 * n + 1 : nullptr;
     p.kemeny_se = kemeny_se ? d + 3 * n + 2 : nullptr;
+    p.part = d + 3 * n + 3;
+    p.n_parts = parts;
     HIP_TRY(launch_span_assemble(p, s));
     if ((rc = copy_out(diag, d, sizeof(double) * n, s)) || (rc = copy_out(diag_se, d + n, sizeof(double) * n, s)) ||
         (rc = copy_out(closeness, d + 2 * n, sizeof(double) * n, s)) ||

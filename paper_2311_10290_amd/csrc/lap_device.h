@@ -241,6 +241,8 @@ struct SpanAsmParams {
     long long *blk_sum;                  // [B] scratch
     const long long *s1, *s2;            // [omega]
     double *diag, *diag_se, *closeness, *trace, *kemeny, *kemeny_se;   // any may be null (diag needed for the rest)
+    double *part;                        // [n_parts] per-workgroup partial traces
+    int64_t n_parts;
 };
 
 }  // namespace lap

@@ -226,14 +226,17 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
 }
 
 // ------------------------------------------------------------------ assembly
-// One workgroup, fixed-order reductions.  Alg. 1's last loop per block b of
-// omega_b samples: est_b(u) = X1_b(u)/omega_b - 2 X2_b(u)/(n omega_b) +
-// sum_w X2_b(w)/(n^2 omega_b); the estimate uses the sums over all blocks,
-// the standard error the spread of the block estimates.  Closeness is
-// (n-1)/(Tr + n diag(u)).  Alg. 3: kappa = mean over samples of s1 - s2/2m.
-constexpr int kAsmThreads = 1024;
+// Alg. 1's last loop per block b of omega_b samples: est_b(u) = X1_b(u)/omega_b
+// - 2 X2_b(u)/(n omega_b) + sum_w X2_b(w)/(n^2 omega_b); the estimate uses the
+// sums over all blocks, the standard error the spread of the block estimates.
+// Closeness is (n-1)/(Tr + n diag(u)).  Alg. 3: kappa = mean over samples of
+// s1 - s2/2m.  Three launches with fixed-order reductions: block sums of X2
+// (exact integers), per-node estimates with per-workgroup partial traces,
+// then the trace, closeness and Kemeny's constant.
+constexpr int kAsmThreads = 256;
 
-__device__ double asm_sum(double v, double *sh) {
+template <class T>
+__device__ T asm_reduce(T v, T *sh) {
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
@@ -241,88 +244,84 @@ __device__ double asm_sum(double v, double *sh) {
         if (t < off) sh[t] += sh[t + off];
         __syncthreads();
     }
-    const double r = sh[0];
+    const T r = sh[0];
     __syncthreads();
     return r;
 }
 
-__device__ long long asm_sum_ll(long long v, long long *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = kAsmThreads / 2; off > 0; off >>= 1) {
-        if (t < off) sh[t] += sh[t + off];
-        __syncthreads();
-    }
-    const long long r = sh[0];
-    __syncthreads();
-    return r;
+// grid = B: blk_sum[b] = sum_u X2_b(u)
+__global__ __launch_bounds__(kAsmThreads) void span_blksum_kernel(SpanAsmParams p) {
+    __shared__ long long sh[kAsmThreads];
+    const int64_t b = blockIdx.x;
+    const long long *X2 = (const long long *)p.X2 + b * p.n;
+    long long acc = 0;
+    for (int64_t u = threadIdx.x; u < p.n; u += kAsmThreads) acc += X2[u];
+    const long long r = asm_reduce(acc, sh);
+    if (threadIdx.x == 0) p.blk_sum[b] = r;
 }
 
-__global__ __launch_bounds__(kAsmThreads) void span_assemble_kernel(SpanAsmParams p) {
-    __shared__ double shd[kAsmThreads];
-    __shared__ long long shl[kAsmThreads];
-    const int t = threadIdx.x;
+// grid over nodes: diag, diag_se; part[blockIdx] = this workgroup's sum of diag
+__global__ __launch_bounds__(kAsmThreads) void span_diag_kernel(SpanAsmParams p) {
+    __shared__ double sh[kAsmThreads];
     const int64_t n = p.n;
-    const double nn = (double)n;
+    const double nn = (double)n, om = (double)p.omega;
     const long long *X1 = (const long long *)p.X1, *X2 = (const long long *)p.X2;
-    if (p.diag) {
-        // block sums of X2 (exact integers) and their total
-        long long tot = 0;
+    long long tot = 0;
+    for (int32_t b = 0; b < p.B; ++b) tot += p.blk_sum[b];
+    const int64_t u = (int64_t)blockIdx.x * kAsmThreads + threadIdx.x;
+    double d = 0.0;
+    if (u < n) {
+        long long x1 = 0, x2 = 0;
+        double bs = 0.0;
+        auto block_est = [&](int32_t b) {
+            const double ob = (double)p.blk_n[b];
+            return (double)X1[(int64_t)b * n + u] / ob - 2.0 * (double)X2[(int64_t)b * n + u] / (nn * ob) +
+                   (double)p.blk_sum[b] / (nn * nn * ob);
+        };
         for (int32_t b = 0; b < p.B; ++b) {
-            long long acc = 0;
-            for (int64_t u = t; u < n; u += kAsmThreads) acc += X2[(int64_t)b * n + u];
-            const long long sb = asm_sum_ll(acc, shl);
-            if (t == 0) p.blk_sum[b] = sb;
-            tot += sb;
+            x1 += X1[(int64_t)b * n + u];
+            x2 += X2[(int64_t)b * n + u];
+            bs += block_est(b);
         }
-        __syncthreads();
-        const double om = (double)p.omega;
-        double tr = 0.0;
-        for (int64_t u = t; u < n; u += kAsmThreads) {
-            long long x1 = 0, x2 = 0;
-            double bs = 0.0;
-            auto block_est = [&](int32_t b) {
-                const double ob = (double)p.blk_n[b];
-                return (double)X1[(int64_t)b * n + u] / ob - 2.0 * (double)X2[(int64_t)b * n + u] / (nn * ob) +
-                       (double)p.blk_sum[b] / (nn * nn * ob);
-            };
+        d = (double)x1 / om - 2.0 * (double)x2 / (nn * om) + (double)tot / (nn * nn * om);
+        p.diag[u] = d;
+        if (p.diag_se) {
+            const double B = (double)p.B, mean = bs / B;
+            double q = 0.0;
             for (int32_t b = 0; b < p.B; ++b) {
-                x1 += X1[(int64_t)b * n + u];
-                x2 += X2[(int64_t)b * n + u];
-                bs += block_est(b);
+                const double e = block_est(b) - mean;
+                q += e * e;
             }
-            const double d = (double)x1 / om - 2.0 * (double)x2 / (nn * om) + (double)tot / (nn * nn * om);
-            p.diag[u] = d;
-            if (p.diag_se) {
-                const double B = (double)p.B, mean = bs / B;
-                double q = 0.0;
-                for (int32_t b = 0; b < p.B; ++b) {
-                    const double e = block_est(b) - mean;
-                    q += e * e;
-                }
-                p.diag_se[u] = p.B > 1 ? sqrt(q / (B - 1.0)) / sqrt(B) : __builtin_nan("");
-            }
-            tr += d;
+            p.diag_se[u] = p.B > 1 ? sqrt(q / (B - 1.0)) / sqrt(B) : __builtin_nan("");
         }
-        const double Tr = asm_sum(tr, shd);
-        if (p.closeness)
-            for (int64_t u = t; u < n; u += kAsmThreads) p.closeness[u] = n > 1 ? (nn - 1.0) / (Tr + nn * p.diag[u]) : 0.0;
-        if (t == 0 && p.trace) *p.trace = Tr;
+    }
+    const double r = asm_reduce(d, sh);
+    if (threadIdx.x == 0) p.part[blockIdx.x] = r;
+}
+
+// one workgroup: Tr from the partial sums (fixed order), Kemeny's constant
+__global__ __launch_bounds__(kAsmThreads) void span_final_kernel(SpanAsmParams p) {
+    __shared__ double sh[kAsmThreads];
+    const int t = threadIdx.x;
+    if (p.diag) {
+        double acc = 0.0;
+        for (int64_t i = t; i < p.n_parts; i += kAsmThreads) acc += p.part[i];
+        const double Tr = asm_reduce(acc, sh);
+        if (t == 0) *p.trace = Tr;
     }
     if (p.kemeny) {
         const double two_m = (double)p.two_m;
         double acc = 0.0;
         for (int64_t i = t; i < p.omega; i += kAsmThreads) acc += (double)p.s1[i] - (double)p.s2[i] / two_m;
-        const double mean = asm_sum(acc, shd) / (double)p.omega;
+        const double mean = asm_reduce(acc, sh) / (double)p.omega;
         double sq = 0.0;
         for (int64_t i = t; i < p.omega; i += kAsmThreads) {
             const double z = (double)p.s1[i] - (double)p.s2[i] / two_m - mean;
             sq += z * z;
         }
-        const double SQ = asm_sum(sq, shd);
+        const double SQ = asm_reduce(sq, sh);
         if (t == 0) {
-            *p.kemeny = n > 1 ? mean : 0.0;
+            *p.kemeny = p.n > 1 ? mean : 0.0;
             if (p.kemeny_se)
                 *p.kemeny_se = p.omega > 1 ? sqrt(SQ / ((double)p.omega - 1.0)) / sqrt((double)p.omega)
                                            : __builtin_nan("");
@@ -330,8 +329,23 @@ __global__ __launch_bounds__(kAsmThreads) void span_assemble_kernel(SpanAsmParam
     }
 }
 
+// grid over nodes: closeness from the trace
+__global__ __launch_bounds__(kAsmThreads) void span_closeness_kernel(SpanAsmParams p) {
+    const int64_t u = (int64_t)blockIdx.x * kAsmThreads + threadIdx.x;
+    const double nn = (double)p.n;
+    if (u < p.n) p.closeness[u] = p.n > 1 ? (nn - 1.0) / (*p.trace + nn * p.diag[u]) : 0.0;
+}
+
+int64_t span_assemble_parts(int64_t n) { return (n + kAsmThreads - 1) / kAsmThreads; }
+
 hipError_t launch_span_assemble(const SpanAsmParams &p, hipStream_t s) {
-    hipLaunchKernelGGL(span_assemble_kernel, dim3(1), dim3(kAsmThreads), 0, s, p);
+    const unsigned g = (unsigned)span_assemble_parts(p.n);
+    if (p.diag) {
+        hipLaunchKernelGGL(span_blksum_kernel, dim3((unsigned)p.B), dim3(kAsmThreads), 0, s, p);
+        hipLaunchKernelGGL(span_diag_kernel, dim3(g), dim3(kAsmThreads), 0, s, p);
+    }
+    hipLaunchKernelGGL(span_final_kernel, dim3(1), dim3(kAsmThreads), 0, s, p);
+    if (p.diag && p.closeness) hipLaunchKernelGGL(span_closeness_kernel, dim3(g), dim3(kAsmThreads), 0, s, p);
     return hipGetLastError();
 }
 
