@@ -238,6 +238,49 @@ def bench_landmark(lap, gg):
     return res
 
 
+def bench_kc_families(lap, gg, n):
+    """Kemeny's constant of synthetic families (the paper's Sec. 6 study on
+    BA, ER and hyperbolic graphs): BA with m = 2..6; ER with average degree
+    200..1000 (p = 2..10 x 1e-4 at 1e6 nodes); hyperbolic with gamma =
+    2.2..3.0 and average degree 10 (largest component); 256 samples each,
+    all 15 graphs in one batched launch."""
+    import torch
+    t0 = time.perf_counter()
+    jobs, labels = [], []
+    for m in (2, 3, 4, 5, 6):
+        s, d = gg.barabasi_albert(n, m, 100 + m)
+        jobs.append(dict(n=n, src=s, dst=d, keep_lcc=True, root=-1, omega=256, seed=1))
+        labels.append(f"BA m={m}")
+    for k in (200, 400, 600, 800, 1000):
+        s, d = gg.erdos_renyi(n, k / (n - 1), 200 + k)
+        jobs.append(dict(n=n, src=s, dst=d, keep_lcc=True, root=-1, omega=256, seed=1))
+        labels.append(f"ER avg degree {k}")
+    for gamma in (2.2, 2.4, 2.6, 2.8, 3.0):
+        s, d = gg.hyperbolic(n, 10.0, gamma, 300 + int(round(gamma * 10)))
+        jobs.append(dict(n=n, src=s, dst=d, keep_lcc=True, root=-1, omega=256, seed=1))
+        labels.append(f"hyperbolic gamma={gamma}")
+    b = lap.Batch(jobs)
+    gen_s = time.perf_counter() - t0
+    tuning = lap.Batch.tuning()
+    b.run(tuning)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.run(tuning)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    rows = []
+    for j, lab in enumerate(labels):
+        r = b.result(j)
+        rows.append({"graph": lab, "n_lcc": int(b.info[j]["n"]), "kemeny": float(r["kemeny"][0]),
+                     "kemeny_se": float(r["kemeny_se"][0]),
+                     "kemeny_over_n": float(r["kemeny"][0]) / b.info[j]["n"]})
+    st = b.stats()
+    b.close()
+    return {"workload": f"15 synthetic graphs, n={n}, 256 samples each, one batched launch", "s": dt,
+            "prepare_s": gen_s, "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) / dt,
+            "graphs": rows}
+
+
 def _serial(lap, srv, qs, qid0):
     """The same queries one at a time: each is submitted when the previous
     one has completed (no batching across queries).  Returns the wall time."""
@@ -351,6 +394,8 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-spantree", action="store_true")
     ap.add_argument("--no-landmark", action="store_true")
+    ap.add_argument("--no-kc-families", action="store_true")
+    ap.add_argument("--kc-n", type=int, default=100_000)
     ap.add_argument("--serve-queries", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
@@ -465,6 +510,9 @@ def main():
     if not args.no_landmark:
         log("landmark study")
         res["landmark"] = bench_landmark(lap, gg)
+    if not args.no_kc_families:
+        log("Kemeny's constant of synthetic families")
+        res["kc_families"] = bench_kc_families(lap, gg, args.kc_n)
     if not args.no_batch:
         res["batched"] = bench_batch(lap, gg, args.batch_jobs)
     if not args.no_serve:

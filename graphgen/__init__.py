@@ -45,6 +45,10 @@ def _load():
         lib.gg_rmat.restype = i64
         lib.gg_is_connected.argtypes = [i64, i64, p32, p32]
         lib.gg_is_connected.restype = i32
+        lib.gg_hyperbolic.argtypes = [i64, dbl, dbl, u64, i64, p32, p32]
+        lib.gg_hyperbolic.restype = i64
+        lib.gg_hyperbolic_points.argtypes = [i64, dbl, dbl, u64, ctypes.c_void_p, ctypes.c_void_p]
+        lib.gg_hyperbolic_points.restype = dbl
         _lib = lib
     return _lib
 
@@ -103,6 +107,31 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
     if got != ne:
         raise RuntimeError(f"gg_rmat failed ({got})")
     return src, dst
+
+
+def hyperbolic(n: int, avg_deg: float, gamma: float, seed: int):
+    """Random hyperbolic graph (threshold model): power-law degrees with
+    exponent gamma > 2 and average degree about avg_deg (raw pairs; may be
+    disconnected)."""
+    lib = _load()
+    cap = int(n * avg_deg * 0.75 + 1024)
+    while True:
+        src = np.empty(cap, np.int32)
+        dst = np.empty(cap, np.int32)
+        cnt = lib.gg_hyperbolic(n, float(avg_deg), float(gamma), seed, cap, _p32(src), _p32(dst))
+        if cnt < 0:
+            raise ValueError("bad hyperbolic-graph arguments")
+        if cnt <= cap:
+            return src[:cnt].copy(), dst[:cnt].copy()
+        cap = int(cnt)
+
+
+def hyperbolic_points(n: int, avg_deg: float, gamma: float, seed: int):
+    """(angles, radii, R) of the points hyperbolic() joins, for brute-force checks."""
+    th = np.empty(n)
+    r = np.empty(n)
+    R = _load().gg_hyperbolic_points(n, float(avg_deg), float(gamma), seed, th.ctypes.data, r.ctypes.data)
+    return th, r, R
 
 
 # ---------------------------------------------------------------- small graphs

@@ -152,3 +152,125 @@ int32_t gg_is_connected(int64_t n, int64_t n_edges, const int32_t *src, const in
     free(par);
     return comps == 1 ? 1 : 0;
 }
+
+/* ------------------------------------------------------------ hyperbolic */
+/*
+ * Random hyperbolic graph, threshold model (Krioukov, Papadopoulos, Kitsak,
+ * Vahdat, Boguna, Phys. Rev. E 82, 2010): n points in a hyperbolic disk of
+ * radius R, angles uniform, radii with density alpha sinh(alpha r) /
+ * (cosh(alpha R) - 1), alpha = (gamma - 1) / 2; two points are joined when
+ * their hyperbolic distance is at most R.  R is set from the target average
+ * degree k by the model's large-n relation k = (2/pi) xi^2 n e^{-R/2},
+ * xi = alpha / (alpha - 1/2) (requires gamma > 2).
+ * Pairs are found band by band (radial bands holding equal numbers of
+ * points, each sorted by angle): a point only looks, in each band, at the
+ * angular window within which a point of that band's smallest radius could
+ * be close enough, then tests the exact distance.  Each edge is emitted once,
+ * from its endpoint of smaller (radius, id).
+ * Returns the number of edges (written only while below cap), -1 on bad
+ * arguments or allocation failure.
+ */
+typedef struct { double th; double r; int32_t id; } gg_pt;
+
+static int gg_cmp_th(const void *a, const void *b) {
+    double x = ((const gg_pt *)a)->th, y = ((const gg_pt *)b)->th;
+    return (x > y) - (x < y);
+}
+static int gg_cmp_r(const void *a, const void *b) {
+    double x = ((const gg_pt *)a)->r, y = ((const gg_pt *)b)->r;
+    if (x != y) return (x > y) - (x < y);
+    return ((const gg_pt *)a)->id - ((const gg_pt *)b)->id;
+}
+
+/* largest angular gap at which radii r1, r2 are within distance R */
+static double gg_dtheta(double r1, double r2, double coshR) {
+    double den = sinh(r1) * sinh(r2);
+    if (den <= 0.0) return M_PI;
+    double c = (cosh(r1) * cosh(r2) - coshR) / den;
+    if (c <= -1.0) return M_PI;
+    if (c >= 1.0) return 0.0;
+    return acos(c);
+}
+
+int64_t gg_hyperbolic(int64_t n, double avg_deg, double gamma, uint64_t seed, int64_t cap,
+                      int32_t *src, int32_t *dst) {
+    if (n < 2 || avg_deg <= 0.0 || gamma <= 2.0) return -1;
+    const double alpha = 0.5 * (gamma - 1.0);
+    const double xi = alpha / (alpha - 0.5);
+    const double R = 2.0 * log(2.0 * xi * xi * (double)n / (M_PI * avg_deg));
+    const double coshR = cosh(R);
+    gg_rng rng;
+    rng_seed(&rng, seed);
+    gg_pt *p = (gg_pt *)malloc(sizeof(gg_pt) * (size_t)n);
+    if (!p) return -1;
+    const double top = cosh(alpha * R) - 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+        p[i].th = 2.0 * M_PI * rng_unif(&rng);
+        p[i].r = acosh(1.0 + rng_unif(&rng) * top) / alpha;
+        p[i].id = (int32_t)i;
+    }
+    /* bands of equal size in radial order, each sorted by angle */
+    qsort(p, (size_t)n, sizeof(gg_pt), gg_cmp_r);
+    int64_t nb = 1;
+    while ((1LL << nb) < n) ++nb;
+    if (nb < 4) nb = 4;
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+    double *rmin = (double *)malloc(sizeof(double) * (size_t)nb);
+    if (!start || !rmin) { free(p); free(start); free(rmin); return -1; }
+    for (int64_t b = 0; b <= nb; ++b) start[b] = b * n / nb;
+    for (int64_t b = 0; b < nb; ++b) {
+        rmin[b] = start[b] < start[b + 1] ? p[start[b]].r : R;
+        qsort(p + start[b], (size_t)(start[b + 1] - start[b]), sizeof(gg_pt), gg_cmp_th);
+    }
+    int64_t cnt = 0;
+    for (int64_t b0 = 0; b0 < nb; ++b0)
+        for (int64_t i = start[b0]; i < start[b0 + 1]; ++i) {
+            const gg_pt u = p[i];
+            const double chu = cosh(u.r), shu = sinh(u.r);
+            for (int64_t b = b0; b < nb; ++b) {
+                const int64_t lo = start[b], hi = start[b + 1];
+                if (lo >= hi) continue;
+                const double dth = gg_dtheta(u.r, rmin[b] > u.r ? rmin[b] : u.r, coshR);
+                if (dth <= 0.0) continue;
+                /* scan the angular window [th - dth, th + dth] (wrapping) */
+                double a0 = u.th - dth, a1 = u.th + dth;
+                for (int pass = 0; pass < 3; ++pass) {
+                    double wl, wh;
+                    if (pass == 0) { wl = a0 < 0.0 ? 0.0 : a0; wh = a1 > 2.0 * M_PI ? 2.0 * M_PI : a1; }
+                    else if (pass == 1) { if (a0 >= 0.0) continue; wl = a0 + 2.0 * M_PI; wh = 2.0 * M_PI; }
+                    else { if (a1 <= 2.0 * M_PI) continue; wl = 0.0; wh = a1 - 2.0 * M_PI; }
+                    if (dth >= M_PI) { if (pass > 0) continue; wl = 0.0; wh = 2.0 * M_PI; }
+                    int64_t l = lo, h = hi;              /* first index with th >= wl */
+                    while (l < h) { int64_t m = (l + h) / 2; if (p[m].th < wl) l = m + 1; else h = m; }
+                    for (int64_t j = l; j < hi && p[j].th <= wh; ++j) {
+                        const gg_pt w = p[j];
+                        if (w.r < u.r || (w.r == u.r && w.id <= u.id)) continue;
+                        const double cd = chu * cosh(w.r) - shu * sinh(w.r) * cos(u.th - w.th);
+                        if (cd <= coshR) {
+                            if (cnt < cap) { src[cnt] = u.id; dst[cnt] = w.id; }
+                            ++cnt;
+                        }
+                    }
+                }
+            }
+        }
+    free(p); free(start); free(rmin);
+    return cnt;
+}
+
+/* The points gg_hyperbolic places for the same arguments (node i's angle and
+ * radius), and the disk radius R; for tests that check the pairs by brute force. */
+double gg_hyperbolic_points(int64_t n, double avg_deg, double gamma, uint64_t seed, double *th, double *r) {
+    if (n < 2 || avg_deg <= 0.0 || gamma <= 2.0) return -1.0;
+    const double alpha = 0.5 * (gamma - 1.0);
+    const double xi = alpha / (alpha - 0.5);
+    const double R = 2.0 * log(2.0 * xi * xi * (double)n / (M_PI * avg_deg));
+    gg_rng rng;
+    rng_seed(&rng, seed);
+    const double top = cosh(alpha * R) - 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+        th[i] = 2.0 * M_PI * rng_unif(&rng);
+        r[i] = acosh(1.0 + rng_unif(&rng) * top) / alpha;
+    }
+    return R;
+}

@@ -1,5 +1,6 @@
 """Input generators are deterministic and produce the advertised shapes."""
 import numpy as np
+import pytest
 
 import graphgen as gg
 
@@ -44,3 +45,34 @@ def test_batch_and_query_recipes():
     assert ns.min() >= 1000 and ns.max() <= 200_000 and om.min() >= 256 and om.max() <= 4096
     q = gg.query_stream(1000, 500, 100.0)
     assert len(q) == 500 and all(q[i]["t"] < q[i + 1]["t"] for i in range(499))
+
+
+@pytest.mark.parametrize("gamma", [2.2, 2.6, 3.0])
+def test_hyperbolic_pairs_equal_brute_force(gamma):
+    """The band search emits exactly the pairs within hyperbolic distance R."""
+    n = 1500
+    s, d = gg.hyperbolic(n, 8.0, gamma, 11)
+    th, r, R = gg.hyperbolic_points(n, 8.0, gamma, 11)
+    ch = (np.cosh(r)[:, None] * np.cosh(r)[None, :]
+          - np.sinh(r)[:, None] * np.sinh(r)[None, :] * np.cos(th[:, None] - th[None, :]))
+    close = ch <= np.cosh(R)
+    np.fill_diagonal(close, False)
+    want = {(int(a), int(b)) for a, b in zip(*np.nonzero(np.triu(close)))}
+    got = {(min(int(a), int(b)), max(int(a), int(b))) for a, b in zip(s, d)}
+    assert len(got) == len(s)                       # every pair once
+    # pairs at distance within rounding of R may go either way; all others agree
+    tie = np.abs(ch - np.cosh(R)) <= 1e-9 * np.cosh(R)
+    diff = got ^ want
+    assert all(tie[a, b] for a, b in diff), len(diff)
+
+
+def test_hyperbolic_degree_tail():
+    """Average degree near the target and a heavier tail for smaller gamma."""
+    n = 100_000
+    tails = []
+    for gamma in (2.5, 3.0):
+        s, d = gg.hyperbolic(n, 10.0, gamma, 3)
+        deg = np.bincount(np.concatenate([s, d]), minlength=n)
+        assert 7.0 < deg.mean() < 13.0
+        tails.append(np.sort(deg)[-n // 1000:].mean())
+    assert tails[0] > 1.5 * tails[1]
