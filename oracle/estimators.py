@@ -44,7 +44,8 @@ def closeness(diag):
 def kirchhoff(diag):
     """Kirchhoff index n * Tr(L^dagger) (= sum over node pairs of resistance
     distance).  The text at the end of Sec. 5 names Tr(L^dagger); the factor n
-    is the standard definition's (see the design doc readings)."""
+    comes from the standard definition as the pair sum of resistances, which
+    the library reports beside Tr(L^dagger) itself."""
     return len(diag) * math.fsum(np.asarray(diag).tolist())
 
 
