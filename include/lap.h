@@ -294,6 +294,24 @@ int lap_spantree(lap_graph *g, const lap_sample_args *a, int64_t *X1, int64_t *X
 int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, double *diag, double *diag_se, double *closeness,
                           double *kemeny, double *kemeny_se, void *hip_stream);
 
+/*
+ * lap_loop_included -- loop-included paths of the Wilson stacks (Sec. 3.4,
+ * the loop-erased-walk interpretation of L_v^{-1}): for every sample i of a,
+ * the path that starts where absorbed walk i of kind tag starts (1: uniform
+ * over V, counter (i | 1<<56, 0, 0, qid); 2: stationary, (i | 2<<56, 0, 0,
+ * qid)) and at its c-th departure from u moves to stack entry S_i[u][c] --
+ * the same draw the sampler used -- until it reaches v.  Such a path is
+ * distributed as a v-absorbed walk from its start, so its departures
+ * estimate the same quantities as the walks of lap_sample_forests
+ * (LAP_WANT_Y2_UNIFORM / LAP_WANT_Y2_PI) without draws of their own.
+ * Outputs (int64; host unless LAP_OUT_DEVICE; either may be NULL):
+ *   Y2  [B][n]        departures per node, per block of samples;
+ *   len [n_samples]   departures per path.
+ * Scratch: 4 bytes per node per path in flight (at most 48 GiB).
+ */
+int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t tag, int64_t *Y2, int64_t *len,
+                      void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /*
@@ -389,8 +407,8 @@ const char *lap_last_error(void);
 /* Kernel timing: when enabled, every kernel launch of the library is
  * bracketed by HIP events on the stream it runs on; lap_prof_read returns
  * the accumulated milliseconds and launch count for a kernel name
- * ("wilson_wave", "wilson_lane", "wilson_group", "spantree", "absorbed",
- * "assemble", "batch", "batch_assemble").  Returns
+ * ("wilson_wave", "wilson_lane", "wilson_group", "spantree", "loop_included",
+ * "absorbed", "assemble", "batch", "batch_assemble").  Returns
  * LAP_EINVAL for an unknown name. */
 int lap_prof_enable(int on);
 int lap_prof_reset(void);

@@ -55,6 +55,8 @@ def lib():
         L.oracle_query_walks.argtypes = [i64, P, P, i32, u64, u32, u64, i32, i32, i32, i32, i64, i64,
                                          P, P, P, P]
         L.oracle_query_walks.restype = i32
+        L.oracle_loop_included.argtypes = [i64, P, P, i32, u64, u32, u64, i32, i64, i64, i64, i32, P, P, i32]
+        L.oracle_loop_included.restype = i32
         L.oracle_bfs_tree.argtypes = [i64, P, P, i32, P]
         L.oracle_bfs_tree.restype = i64
         L.oracle_spantree_tree.argtypes = [i64, P, i32, P, P, P, P, P, P, P]
@@ -235,3 +237,19 @@ def spantree(g, root, n_samples, seed, kind, *, stream=0, qid=0, sample_begin=0,
     if st != 0:
         raise RuntimeError(f"oracle_spantree failed ({st})")
     return dict(X1=X1, X2=X2, s1=s1, s2=s2)
+
+
+def loop_included(g, root, n_paths, seed, tag, *, stream=0, qid=0, sample_begin=0, omega_total=None, B=1,
+                  want_y2=True, threads=0):
+    """Loop-included paths of Wilson samples, started like absorbed walks of
+    kind tag: departures per node (Y2 [B][n]) and per path (len)."""
+    n, rp, col = _graph(g)
+    if omega_total is None:
+        omega_total = sample_begin + n_paths
+    Y2 = np.zeros((B, n), np.int64) if want_y2 else None
+    ln = np.zeros(n_paths, np.int64)
+    st = lib().oracle_loop_included(n, _p(rp), _p(col), int(root), seed, stream, qid, tag, sample_begin, n_paths,
+                                    omega_total, B, _p(Y2), _p(ln), threads)
+    if st != 0:
+        raise MemoryError("oracle_loop_included failed")
+    return dict(Y2=Y2, len=ln)

@@ -543,3 +543,73 @@ int32_t oracle_spantree(int64_t n, const int64_t *rp, const int32_t *col, int32_
     free(bfs_par); free(wt);
     return status;
 }
+
+/*
+ * Loop-included paths of Wilson samples [sample_begin, sample_begin +
+ * n_paths) of an omega_total-sample run (Sec. 3.4): path i starts where
+ * absorbed walk i of kind tag starts (tag 1 uniform over V, tag 2 stationary)
+ * and follows the bottom entries of sample i's stacks until the root.  By the
+ * loop-erased-walk lemma (Sec. 3.4) it is distributed as a v-absorbed walk
+ * from its start, so its departures estimate the same quantities as Alg. 2's
+ * and Alg. 4's walks, without fresh draws.  Y2 ([B][n], may be NULL) gets
+ * the departures per node in block floor(i*B/omega_total); len_per_path
+ * ([n_paths], may be NULL) the number of departures.  Returns 0, -1 on
+ * allocation failure.
+ */
+int32_t oracle_loop_included(int64_t n, const int64_t *rp, const int32_t *col, int32_t root,
+                             uint64_t seed, uint32_t stream, uint64_t qid, int32_t tag,
+                             int64_t sample_begin, int64_t n_paths, int64_t omega_total, int32_t B,
+                             int64_t *Y2, int64_t *len_per_path, int32_t n_threads) {
+    if (B < 1) B = 1;
+    const uint64_t k0 = seed, k1 = make_key1(stream, root);
+    const int64_t nnz = rp[n];
+    int32_t status = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        int64_t *pos = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+        int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!pos || !touched) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            status = -1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+            for (int64_t q = 0; q < n_paths; ++q) {
+                const int64_t i = sample_begin + q;
+                const uint64_t x0 = walk_draw(k0, k1, (uint64_t)tag, (uint64_t)i, 0, 0, qid);
+                int32_t u;
+                if (tag == 1) u = (int32_t)oracle_map_below(x0, (uint64_t)n);
+                else if (nnz > 0) u = col[oracle_map_below(x0, (uint64_t)nnz)];
+                else u = root;
+                draw_ctx dc;
+                memset(&dc, 0, sizeof dc);
+                dc.rp = rp; dc.col = col; dc.k0 = k0; dc.k1 = k1; dc.c0 = (uint64_t)i; dc.qid = qid;
+                const int64_t b = (int64_t)(((__int128)i * B) / omega_total);
+                int64_t len = 0, nt = 0;
+                while (u != root) {
+                    if (pos[u] == 0) touched[nt++] = u;
+                    const int32_t w = stack_entry(&dc, u, pos[u]);
+                    pos[u] += 1;
+                    if (Y2) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                        Y2[b * n + u] += 1;
+                    }
+                    ++len;
+                    u = w;
+                }
+                for (int64_t t = 0; t < nt; ++t) pos[touched[t]] = 0;
+                if (len_per_path) len_per_path[q] = len;
+            }
+        }
+        free(pos); free(touched);
+    }
+    return status;
+}

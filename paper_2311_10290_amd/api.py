@@ -198,6 +198,16 @@ class Graph:
                                                     _stream(stream)))
         return res
 
+    def loop_included(self, omega, seed, tag, root=-1, *, B=1, sample_begin=0, n_total=0, mode=0, pool=0, group=0,
+                      stream_id=0, qid=0, timeout_s=0.0, stream=None):
+        """Loop-included paths of the Wilson stacks (lap_loop_included): Y2 [B][n], len [omega]."""
+        a = self._args(omega, seed, root, 0, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s,
+                       group=group)
+        out = dict(Y2=np.zeros((B, self.n), np.int64), len=np.zeros(omega, np.int64))
+        _check(load_library().lap_loop_included(self._h, ctypes.byref(a), int(tag), _ptr(out["Y2"]),
+                                                _ptr(out["len"]), _stream(stream)))
+        return out
+
     def landmark_traces(self, roots, omega, seed, stream=None):
         """Tr((I-P_v)^{-1}) estimate (mean Wilson draws) and its SE for each root."""
         roots = np.ascontiguousarray(roots, np.int32)

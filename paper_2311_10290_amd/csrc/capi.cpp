@@ -617,6 +617,71 @@ extern "C" int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, dou
     return LAP_OK;
 }
 
+// ------------------------------------------------------ loop-included paths
+extern "C" int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t tag, int64_t *Y2, int64_t *len,
+                                 void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (tag != 1 && tag != 2) return fail(LAP_EINVAL, "tag must be 1 (uniform start) or 2 (stationary start)");
+    Resolved r;
+    int rc = resolve_args(g, a, 0, nullptr, r);
+    if (rc != LAP_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    Timer tm;
+    const int64_t n = g->csr.n;
+    const int64_t slots =
+        std::max<int64_t>(1, std::min<int64_t>(r.slots, ((int64_t)48 << 30) / (4 * std::max<int64_t>(n, 1))));
+    if (g->loop_cnt.ensure(sizeof(int32_t) * (size_t)slots * n + 8) ||
+        g->loop_y2.ensure(sizeof(uint64_t) * (size_t)r.B * n) || g->loop_len.ensure(sizeof(int64_t) * r.omega))
+        return fail(LAP_ENOMEM, "cannot allocate loop-included path workspace");
+    HIP_TRY(launch_fill_u64(g->loop_y2.as<uint64_t>(), 0ull, (int64_t)r.B * n, s));
+    const double tmo = a->timeout_s > 0 ? a->timeout_s : 120.0;
+    int64_t acc[kNumStats] = {0};
+    for (int64_t done = 0; done < r.omega; done += slots) {
+        Resolved rr = r;
+        rr.omega = std::min(slots, r.omega - done);
+        rr.begin = r.begin + done;
+        rr.slots = rr.omega;
+        rr.wilson = true;
+        rr.y2u = rr.y2p = false;
+        RunOut o;
+        if ((rc = run_sampling(g, rr, a, 0, nullptr, false, false, o, s, tm)) != LAP_OK) return rc;
+        HIP_TRY(launch_fill_u64(g->loop_cnt.as<uint64_t>(), 0ull, (rr.omega * n + 1) / 2, s));
+        LoopParams p;
+        std::memset(&p, 0, sizeof p);
+        p.n = n;
+        p.nnz = g->csr.rp[n];
+        p.nbr = g->nbr.as<uint64_t>();
+        p.col = g->col.as<int32_t>();
+        p.root = r.root;
+        p.k0 = a->seed;
+        p.k1 = ((uint64_t)a->stream << 32) | (uint64_t)(uint32_t)r.root;
+        p.qid = a->qid;
+        p.tag = (uint32_t)tag;
+        p.state = g->state.as<uint64_t>();
+        p.slot_epoch = g->epoch.as<uint32_t>();
+        p.cnt = g->loop_cnt.as<int32_t>();
+        p.n_paths = rr.omega;
+        p.sample_begin = rr.begin;
+        p.n_total = r.total;
+        p.n_blocks = r.B;
+        p.y2 = g->loop_y2.as<unsigned long long>();
+        p.len_out = g->loop_len.as<int64_t>() + done;
+        p.err = g->err.as<DevErr>();
+        p.deadline = (uint64_t)(tmo * g->clock_khz * 1000.0);
+        tm.begin("loop_included", s);
+        HIP_TRY(launch_loop_included(p, s));
+        tm.end(s);
+        if ((rc = finish(g, s, tm)) != LAP_OK) return rc;
+        for (int i = 0; i < kNumStats; ++i) acc[i] += g->last_stats[i];
+    }
+    for (int i = 0; i < kNumStats; ++i) g->last_stats[i] = acc[i];
+    if ((rc = copy_out(Y2, g->loop_y2.ptr, sizeof(int64_t) * (size_t)r.B * n, s)) ||
+        (rc = copy_out(len, g->loop_len.ptr, sizeof(int64_t) * r.omega, s)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return LAP_OK;
+}
+
 static lap_sample_args default_args(int32_t root, int64_t omega, uint64_t seed, int32_t B) {
     lap_sample_args a;
     std::memset(&a, 0, sizeof a);

@@ -233,6 +233,25 @@ struct SpanParams {
     DevErr *err;
 };
 
+// Loop-included paths over the trees left in the Wilson state slots (loops.hip)
+struct LoopParams {
+    int64_t n, nnz;
+    const uint64_t *nbr;
+    const int32_t *col;
+    int32_t root;
+    uint64_t k0, k1, qid;
+    uint32_t tag;                  // start like absorbed walk kind 1 (uniform) or 2 (stationary)
+    const uint64_t *state;         // [slots][n]
+    const uint32_t *slot_epoch;    // [slots]
+    int32_t *cnt;                  // [n_paths][n] departures so far, zero before the launch
+    int64_t n_paths, sample_begin, n_total;
+    int32_t n_blocks;
+    unsigned long long *y2;        // [B][n] or null
+    int64_t *len_out;              // [n_paths] of this launch, or null
+    DevErr *err;
+    uint64_t deadline;
+};
+
 struct SpanAsmParams {
     int64_t n, omega, two_m;
     int32_t B;

@@ -105,3 +105,40 @@ def test_single_node_graph_walks_are_empty():
     for tag in (1, 2):
         a = native.absorbed(g, 0, 16, 1, tag)
         assert (a["len"] == 0).all() and (a["Y2"] == 0).all()
+
+
+def test_loop_included_paths_driver():
+    """Loop-included paths of Wilson samples (Sec. 3.4), started where the
+    absorbed walks of the same index start:
+      - each path is the one the single-path routine reads from the stacks;
+      - a path never uses more entries of a stack than the sample drew there
+        (every entry it uses is popped by Wilson's run, or is the top);
+      - departures and lengths have the absorbed walks' expectations."""
+    g = er256()
+    v = csr.landmark(g)
+    r = native.loop_included(g, v, 30, 5, 1)
+    starts = native.absorbed(g, v, 30, 5, 1, want_y2=False, want_start=True)["start"]
+    w = native.wilson(g, v, 30, 5, keep=list(range(30)), want_y1=False)
+    for i in range(30):
+        tr = native.loop_included_path(g.n, v, int(starts[i]), g=g, sample=i, seed=5)
+        assert len(tr) - 1 == r["len"][i]
+        used = np.bincount(tr[:-1], minlength=g.n)
+        assert (used <= w["draws"][i]).all()
+    L = dense.laplacian(g)
+    Lvi = dense.lv_inv(L, v)
+    d = np.diag(L)
+    omega = 20000
+    u = native.loop_included(g, v, omega, 1, 1, B=50)
+    ln = u["len"].astype(float)
+    exact = (Lvi @ d).sum() / g.n
+    assert abs(ln.mean() - exact) < 3.5 * ln.std(ddof=1) / math.sqrt(omega)
+    blocks = u["Y2"] / (omega / 50)
+    want = d / g.n * Lvi.sum(1)
+    z = (blocks.mean(0) - want) / (blocks.std(0, ddof=1) / math.sqrt(50))
+    z = z[np.arange(g.n) != v]
+    assert np.max(np.abs(z)) < 4.8 and np.mean(np.abs(z) < 3) >= 0.97
+    p = native.loop_included(g, v, omega, 2, 2, want_y2=False)
+    lp = p["len"].astype(float)
+    dv = d.copy()
+    dv[v] = 0
+    assert abs(lp.mean() - dv @ Lvi @ dv / d.sum()) < 3.5 * lp.std(ddof=1) / math.sqrt(omega)
