@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "lap_device.h"
+#include "lap_params.h"
 
 namespace lap {
 
