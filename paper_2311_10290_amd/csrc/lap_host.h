@@ -73,7 +73,7 @@ struct lap_graph {
     double clock_khz = 100000.0;
     lap::HostCSR csr;
     int32_t max_deg_node = 0, max_deg = 0;
-    lap::DevBuf rp, nbr, col;
+    lap::DevBuf rp, nbr, col, arcs;   // arcs: per column entry {target, its adjacency record}
     // sampling workspace
     lap::DevBuf state, epoch;
     int64_t state_slots = 0;
@@ -88,7 +88,7 @@ struct lap_graph {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t last_stats[lap::kNumStats] = {0};
     ~lap_graph() {
-        lap::DevBuf *bufs[] = {&rp, &nbr, &col, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
+        lap::DevBuf *bufs[] = {&rp, &nbr, &col, &arcs, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
                           &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount,
                           &bfs_par, &span64, &span32, &span_x, &span_s, &loop_cnt, &loop_y2, &loop_len};
         for (lap::DevBuf *b : bufs) b->release();

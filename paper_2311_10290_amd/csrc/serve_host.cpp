@@ -293,6 +293,7 @@ int launch(lap_server *s, int idx) {
     p.nnz = g->csr.rp[s->n];
     p.nbr = g->nbr.as<uint64_t>();
     p.col = g->col.as<int32_t>();
+    p.arcs = (const ulonglong2 *)g->arcs.ptr;
     p.root = s->cfg.root;
     p.k0 = s->cfg.seed;
     p.k1 = s->k1;

@@ -8,9 +8,11 @@
 
 namespace lap {
 
+// arcs[j] = {target w of CSR slot j, w's adjacency record}: a walk step reads
+// its next node and that node's row in one dependent load
 struct WalkGraph {
     const uint64_t *nbr;
-    const int32_t *col;
+    const ulonglong2 *arcs;
     int64_t n, nnz;
     int32_t root;
     uint64_t k0, k1, qid;
@@ -22,16 +24,24 @@ static inline __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag,
     const uint64_t c0 = (uint64_t)i | ((uint64_t)tag << 56);
     const uint64_t x0 = philox_w0(c0, 0, 0, g.qid, g.k0, g.k1);
     // a graph without edges is the single node v: the walk starts (and ends) there
-    int32_t u = (tag == 1)      ? (int32_t)pick_below(x0, (uint64_t)g.n)
-                : (g.nnz > 0)   ? g.col[pick_below(x0, (uint64_t)g.nnz)]
-                                : g.root;
+    int32_t u = g.root;
+    uint64_t nb = 0;
+    if (tag == 1) {
+        u = (int32_t)pick_below(x0, (uint64_t)g.n);
+        if (u != g.root) nb = g.nbr[u];
+    } else if (g.nnz > 0) {
+        const ulonglong2 a = g.arcs[pick_below(x0, (uint64_t)g.nnz)];
+        u = (int32_t)a.x;
+        nb = a.y;
+    }
     int64_t len = 0;
     while (u != g.root) {
-        const uint64_t nb = g.nbr[u];
         if (y2) atomicAdd(&y2[u], 1ull);
         ++len;
         const uint64_t x = philox_w0(c0, (uint64_t)len, 0, g.qid, g.k0, g.k1);
-        u = g.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
+        const ulonglong2 a = g.arcs[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
+        u = (int32_t)a.x;
+        nb = a.y;
         if ((len & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
             raise_err(err, kErrTimeout, 1);
             return -1;
@@ -53,17 +63,19 @@ static inline __device__ bool query_walk(const WalkGraph &g, int32_t start, uint
                                   uint64_t deadline) {
     const uint64_t c0 = (uint64_t)i | (3ull << 56);
     int32_t u = start;
+    uint64_t nb = (u != g.root) ? g.nbr[u] : 0ull;
     int64_t da = 0, db = 0, steps = 0;
     double nl = 0.0;
     while (u != g.root) {
-        const uint64_t nb = g.nbr[u];
         const uint32_t d = nbr_deg(nb);
         da += (u == a);
         db += (u == b);
         nl += 1.0 / (double)d;
         ++steps;
         const uint64_t x = philox_w0(c0, (uint64_t)steps, sub, g.qid, g.k0, g.k1);
-        u = g.col[nbr_off(nb) + (int64_t)pick_below(x, d)];
+        const ulonglong2 r = g.arcs[nbr_off(nb) + (int64_t)pick_below(x, d)];
+        u = (int32_t)r.x;
+        nb = r.y;
         if ((steps & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
             raise_err(err, kErrTimeout, 2);
             return false;
