@@ -73,7 +73,7 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchParams p) {
             }
             if (!ok) break;
         } else {
-            const WalkGraph g{nbr, p.arcs + jb.col_off, jb.n, jb.nnz, jb.root, jb.k0, jb.k1, jb.qid};
+            const WalkGraph g{nbr, col, nullptr, jb.n, jb.nnz, jb.root, jb.k0, jb.k1, jb.qid};
             const int64_t i = bi.first + lane;
             if (lane < bi.count) {
                 unsigned long long *y2 = bi.kind == 1 ? p.y2 + jb.node_off : nullptr;

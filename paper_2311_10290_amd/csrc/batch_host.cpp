@@ -23,7 +23,7 @@ struct lap_batch {
     std::vector<BatchJobDev> jobs;
     std::vector<std::vector<int32_t>> old_ids;
     int64_t total_n = 0, total_nnz = 0, total_omega = 0, max_n = 0;
-    DevBuf nbr, col, arcs, jobs_d, items_d, counter, state, y1, y2, y1s, len_u, len_p, diag, clo, trace, kem, kem_se,
+    DevBuf nbr, col, jobs_d, items_d, counter, state, y1, y2, y1s, len_u, len_p, diag, clo, trace, kem, kem_se,
         err, stats;
     int64_t state_waves = 0;
     int64_t n_items = 0;
@@ -41,7 +41,7 @@ struct lap_batch {
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (cap) (void)hipStreamDestroy(cap);
-        DevBuf *b[] = {&nbr, &col, &arcs, &jobs_d, &items_d, &counter, &state, &y1, &y2, &y1s, &len_u, &len_p,
+        DevBuf *b[] = {&nbr, &col, &jobs_d, &items_d, &counter, &state, &y1, &y2, &y1s, &len_u, &len_p,
                        &diag, &clo, &trace, &kem, &kem_se, &err, &stats};
         for (DevBuf *x : b) x->release();
     }
@@ -53,7 +53,6 @@ extern "C" int lap_batch_create(const lap_batch_job *jobs, int32_t n_jobs, void 
     if (!b) return fail(LAP_ENOMEM, "host allocation failed");
     std::vector<uint64_t> h_nbr;
     std::vector<int32_t> h_col;
-    std::vector<uint64_t> h_arcs;   // per column entry: {job-local target, its adjacency record}
     for (int32_t j = 0; j < n_jobs; ++j) {
         const lap_batch_job &J = jobs[j];
         if (J.n_samples < 1 || J.n_samples >= ((int64_t)1 << 56) || (J.flags & ~(uint32_t)LAP_KEEP_LCC)) {
@@ -101,10 +100,6 @@ extern "C" int lap_batch_create(const lap_batch_job *jobs, int32_t n_jobs, void 
         b->jobs.push_back(d);
         b->old_ids.push_back(std::move(csr.old_ids));
         h_col.insert(h_col.end(), csr.col.begin(), csr.col.end());
-        for (int64_t j = 0; j < nnz; ++j) {
-            h_arcs.push_back((uint64_t)(uint32_t)csr.col[j]);
-            h_arcs.push_back(h_nbr[(size_t)(d.node_off + csr.col[j])]);
-        }
         b->total_n += n;
         b->total_nnz += nnz;
         b->total_omega += J.n_samples;
@@ -119,7 +114,6 @@ extern "C" int lap_batch_create(const lap_batch_job *jobs, int32_t n_jobs, void 
         b->clock_khz = khz;
     const size_t N = (size_t)b->total_n, W = (size_t)b->total_omega, J = b->jobs.size();
     if (b->nbr.ensure(8 * N) || b->col.ensure(4 * std::max<size_t>(h_col.size(), 1)) ||
-        b->arcs.ensure(8 * std::max<size_t>(h_arcs.size(), 2)) ||
         b->jobs_d.ensure(sizeof(BatchJobDev) * J) || b->counter.ensure(8) || b->y1.ensure(8 * N) ||
         b->y2.ensure(8 * N) || b->y1s.ensure(8 * W) || b->len_u.ensure(8 * W) || b->len_p.ensure(8 * W) ||
         b->diag.ensure(8 * N) || b->clo.ensure(8 * N) || b->trace.ensure(8 * J) || b->kem.ensure(8 * J) ||
@@ -131,7 +125,6 @@ extern "C" int lap_batch_create(const lap_batch_job *jobs, int32_t n_jobs, void 
         return bytes ? hipMemcpyAsync(d.ptr, p, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
     if (up(b->nbr, h_nbr.data(), 8 * N) != hipSuccess || up(b->col, h_col.data(), 4 * h_col.size()) != hipSuccess ||
-        up(b->arcs, h_arcs.data(), 8 * h_arcs.size()) != hipSuccess ||
         up(b->jobs_d, b->jobs.data(), sizeof(BatchJobDev) * J) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
         delete b;
@@ -202,7 +195,6 @@ BatchParams params(lap_batch *b, const lap_batch_tuning &t) {
     p.counter = b->counter.as<unsigned long long>();
     p.nbr = b->nbr.as<uint64_t>();
     p.col = b->col.as<int32_t>();
-    p.arcs = (const ulonglong2 *)b->arcs.ptr;
     p.state = b->state.as<uint64_t>();
     p.max_n = b->max_n;
     p.y1 = b->y1.as<unsigned long long>();
@@ -430,7 +422,6 @@ extern "C" int lap_landmark_traces(lap_graph *g, const int32_t *roots, int32_t n
     p.counter = d_counter.as<unsigned long long>();
     p.nbr = g->nbr.as<uint64_t>();
     p.col = g->col.as<int32_t>();
-    p.arcs = (const ulonglong2 *)g->arcs.ptr;
     p.state = d_state.as<uint64_t>();
     p.max_n = n;
     p.y1 = d_y1.as<unsigned long long>();

@@ -69,17 +69,22 @@ extern "C" int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, con
         return LAP_OK;
     };
     // arcs: the target of every column entry with the target's adjacency
-    // record, so a walk step is one dependent load
-    std::vector<uint64_t> arcs(2 * (size_t)nnz);
-    for (int64_t j = 0; j < nnz; ++j) {
-        const int32_t w = g->csr.col[j];
-        arcs[2 * j] = (uint64_t)(uint32_t)w;
-        arcs[2 * j + 1] = nbr[w];
+    // record, so a walk step is one dependent load; only for column arrays
+    // beyond what the caches hold (smaller graphs keep col and nbr cached,
+    // and the 4x larger records would only add misses)
+    std::vector<uint64_t> arcs;
+    if (4 * nnz >= kArcsMinColBytes) {
+        arcs.resize(2 * (size_t)nnz);
+        for (int64_t j = 0; j < nnz; ++j) {
+            const int32_t w = g->csr.col[j];
+            arcs[2 * j] = (uint64_t)(uint32_t)w;
+            arcs[2 * j + 1] = nbr[w];
+        }
     }
     if ((rc = upload(g->rp, g->csr.rp.data(), sizeof(int64_t) * (nn + 1))) != LAP_OK ||
         (rc = upload(g->nbr, nbr.data(), sizeof(uint64_t) * nn)) != LAP_OK ||
         (rc = upload(g->col, g->csr.col.data(), sizeof(int32_t) * (size_t)nnz)) != LAP_OK ||
-        (rc = upload(g->arcs, arcs.data(), sizeof(uint64_t) * arcs.size())) != LAP_OK ||
+        (!arcs.empty() && (rc = upload(g->arcs, arcs.data(), sizeof(uint64_t) * arcs.size())) != LAP_OK) ||
         hipStreamSynchronize(s) != hipSuccess) {
         delete g;
         return fail(rc == LAP_OK ? LAP_EDEVICE : rc, "graph upload failed");
@@ -250,6 +255,7 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
             std::memset(&ap, 0, sizeof ap);
             ap.n = n;
             ap.nbr = g->nbr.as<uint64_t>();
+            ap.col = g->col.as<int32_t>();
             ap.arcs = (const ulonglong2 *)g->arcs.ptr;
             ap.nnz = g->csr.rp[n];
             ap.root = r.root;
@@ -660,7 +666,7 @@ extern "C" int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t
         p.n = n;
         p.nnz = g->csr.rp[n];
         p.nbr = g->nbr.as<uint64_t>();
-        p.arcs = (const ulonglong2 *)g->arcs.ptr;
+        p.col = g->col.as<int32_t>();
         p.root = r.root;
         p.k0 = a->seed;
         p.k1 = ((uint64_t)a->stream << 32) | (uint64_t)(uint32_t)r.root;

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(64) void absorbed_kernel(AbsorbedParams p) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const uint64_t t0 = wall_clock64();
-    const WalkGraph g{p.nbr, p.arcs, p.n, p.nnz, p.root, p.k0, p.k1, p.qid};
+    const WalkGraph g{p.nbr, p.col, p.arcs, p.n, p.nnz, p.root, p.k0, p.k1, p.qid};
     unsigned long long steps = 0;
     for (int64_t wi = gid; wi < p.n_walks; wi += stride) {
         const int64_t i = p.walk_begin + wi;

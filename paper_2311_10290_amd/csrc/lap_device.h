@@ -136,7 +136,8 @@ struct WaveStats {
 struct AbsorbedParams {
     int64_t n;
     const uint64_t *nbr;
-    const ulonglong2 *arcs;        // [2m] {target, target's adjacency record}
+    const int32_t *col;
+    const ulonglong2 *arcs;        // [2m] {target, target's adjacency record}, or null
     int64_t nnz;
     int32_t root;
     uint64_t k0, k1, qid;

@@ -22,6 +22,9 @@ struct HostCSR {
 int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst, bool keep_lcc,
                    HostCSR &out, std::string &err);
 
+// graphs whose column array has at least this many bytes also get arc records
+constexpr int64_t kArcsMinColBytes = (int64_t)64 << 20;
+
 // BFS tree of the CSR from root, neighbours in ascending order: par[u] is u's
 // parent, -1 at the root.  Returns the number of nodes reached.
 int64_t bfs_parents(const HostCSR &g, int32_t root, std::vector<int32_t> &par);
@@ -73,7 +76,7 @@ struct lap_graph {
     double clock_khz = 100000.0;
     lap::HostCSR csr;
     int32_t max_deg_node = 0, max_deg = 0;
-    lap::DevBuf rp, nbr, col, arcs;   // arcs: per column entry {target, its adjacency record}
+    lap::DevBuf rp, nbr, col, arcs;   // arcs: per column entry {target, its adjacency record}, large graphs only
     // sampling workspace
     lap::DevBuf state, epoch;
     int64_t state_slots = 0;

@@ -31,7 +31,6 @@ struct BatchParams {
     unsigned long long *counter;
     const uint64_t *nbr;   // arena, offsets relative to each job's col_off
     const int32_t *col;    // arena, job-local node ids
-    const ulonglong2 *arcs; // arena, {job-local target, its adjacency record} per column entry
     uint64_t *state;       // [waves][max_n]
     int64_t max_n;
     unsigned long long *y1, *y2;          // [sum n]
@@ -58,7 +57,7 @@ struct ServeParams {
     int64_t n, nnz;
     const uint64_t *nbr;
     const int32_t *col;
-    const ulonglong2 *arcs;
+    const ulonglong2 *arcs;   // or null
     int32_t root;
     uint64_t k0, k1;
     const ServeItem *items;
@@ -96,7 +95,7 @@ struct SpanParams {
 struct LoopParams {
     int64_t n, nnz;
     const uint64_t *nbr;
-    const ulonglong2 *arcs;
+    const int32_t *col;
     int32_t root;
     uint64_t k0, k1, qid;
     uint32_t tag;                  // start like absorbed walk kind 1 (uniform) or 2 (stationary)

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(64) void loop_included_kernel(LoopParams p) {
     const uint32_t ep = p.slot_epoch[slot];
     const uint64_t x0 = philox_w0((uint64_t)i | ((uint64_t)p.tag << 56), 0, 0, p.qid, p.k0, p.k1);
     int32_t u = (p.tag == 1)   ? (int32_t)pick_below(x0, (uint64_t)n)
-                : (p.nnz > 0) ? (int32_t)p.arcs[pick_below(x0, (uint64_t)p.nnz)].x
+                : (p.nnz > 0) ? p.col[pick_below(x0, (uint64_t)p.nnz)]
                               : p.root;
     unsigned long long *y2 = p.y2 ? p.y2 + ((i * (int64_t)p.n_blocks) / p.n_total) * n : nullptr;
     const uint64_t t0 = wall_clock64();
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64) void loop_included_kernel(LoopParams p) {
         const uint64_t x = philox_w0((uint64_t)i, (uint64_t)u, (uint64_t)c, p.qid, p.k0, p.k1);
         if (y2) atomicAdd(&y2[u], 1ull);
         ++len;
-        u = (int32_t)p.arcs[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))].x;
+        u = p.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
         if ((len & 1023) == 0 && (wall_clock64() - t0 > p.deadline || err_set(p.err))) {
             raise_err(p.err, kErrTimeout, 3);
             return;

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeParams p) {
         if (it >= p.n_items) break;
         const ServeItem q = p.items[it];
         uint64_t *out = p.arena + q.out_off;
-        const WalkGraph g{p.nbr, p.arcs, p.n, p.nnz, p.root, p.k0, p.k1, (uint64_t)q.qid};
+        const WalkGraph g{p.nbr, p.col, p.arcs, p.n, p.nnz, p.root, p.k0, p.k1, (uint64_t)q.qid};
         if (q.kind == 0) {
             WaveSampleArgs c;
             c.n = p.n;

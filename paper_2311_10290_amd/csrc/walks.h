@@ -9,14 +9,31 @@
 namespace lap {
 
 // arcs[j] = {target w of CSR slot j, w's adjacency record}: a walk step reads
-// its next node and that node's row in one dependent load
+// its next node and that node's row in one dependent load.  Built only for
+// graphs whose column array is too large for the caches (null otherwise: a
+// step then reads the target from col and its row from nbr).
 struct WalkGraph {
     const uint64_t *nbr;
+    const int32_t *col;
     const ulonglong2 *arcs;
     int64_t n, nnz;
     int32_t root;
     uint64_t k0, k1, qid;
 };
+
+// the move of a walk at a node with adjacency record nb and draw x: the next
+// node and its adjacency record
+static inline __device__ void walk_move(const WalkGraph &g, uint64_t nb, uint64_t x, int32_t &u, uint64_t &nb_next) {
+    const int64_t j = nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb));
+    if (g.arcs) {
+        const ulonglong2 a = g.arcs[j];
+        u = (int32_t)a.x;
+        nb_next = a.y;
+    } else {
+        u = g.col[j];
+        nb_next = (u != g.root) ? g.nbr[u] : 0ull;
+    }
+}
 
 // Returns the walk's length, or -1 if the time limit passed (p.err is set).
 static inline __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag, int64_t i, unsigned long long *y2,
@@ -30,18 +47,15 @@ static inline __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag,
         u = (int32_t)pick_below(x0, (uint64_t)g.n);
         if (u != g.root) nb = g.nbr[u];
     } else if (g.nnz > 0) {
-        const ulonglong2 a = g.arcs[pick_below(x0, (uint64_t)g.nnz)];
-        u = (int32_t)a.x;
-        nb = a.y;
+        u = g.col[pick_below(x0, (uint64_t)g.nnz)];
+        if (u != g.root) nb = g.nbr[u];
     }
     int64_t len = 0;
     while (u != g.root) {
         if (y2) atomicAdd(&y2[u], 1ull);
         ++len;
         const uint64_t x = philox_w0(c0, (uint64_t)len, 0, g.qid, g.k0, g.k1);
-        const ulonglong2 a = g.arcs[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
-        u = (int32_t)a.x;
-        nb = a.y;
+        walk_move(g, nb, x, u, nb);
         if ((len & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
             raise_err(err, kErrTimeout, 1);
             return -1;
@@ -73,9 +87,7 @@ static inline __device__ bool query_walk(const WalkGraph &g, int32_t start, uint
         nl += 1.0 / (double)d;
         ++steps;
         const uint64_t x = philox_w0(c0, (uint64_t)steps, sub, g.qid, g.k0, g.k1);
-        const ulonglong2 r = g.arcs[nbr_off(nb) + (int64_t)pick_below(x, d)];
-        u = (int32_t)r.x;
-        nb = r.y;
+        walk_move(g, nb, x, u, nb);
         if ((steps & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
             raise_err(err, kErrTimeout, 2);
             return false;

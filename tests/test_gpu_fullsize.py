@@ -48,12 +48,18 @@ def test_rmat22_large_workload_counts_bit_exact():
     omega = 512
     keep = [0, omega - 1]
     log(f"rmat22 n={og.n}: HIP path")
-    got = hg.sample_forests(omega, 1, root, B=64, keep=keep)
+    got = hg.sample_forests(omega, 1, root, B=64, keep=keep, y2=True, y2_pi=True)
     log("rmat22: oracle Wilson")
     w = native.wilson(og, root, omega, 1, B=64, keep=keep)
     assert np.array_equal(got["y1"], w["y1"])
     assert np.array_equal(got["Y1"], w["Y1"])
     assert np.array_equal(got["next"], w["next"]) and np.array_equal(got["draws"], w["draws"])
+    # the absorbed walks of this graph step through arc records (large column array)
+    log("rmat22: oracle absorbed walks")
+    a = native.absorbed(og, root, omega, 1, 1, B=64)
+    assert np.array_equal(got["Y2"], a["Y2"]) and np.array_equal(got["len_uniform"], a["len"])
+    p = native.absorbed(og, root, omega, 1, 2, want_y2=False)
+    assert np.array_equal(got["len_pi"], p["len"])
 
 
 def test_batch512_workload_sampled_jobs_bit_exact():
