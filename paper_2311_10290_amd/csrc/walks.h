@@ -21,41 +21,39 @@ struct WalkGraph {
     uint64_t k0, k1, qid;
 };
 
-// the move of a walk at a node with adjacency record nb and draw x: the next
-// node and its adjacency record
-static inline __device__ void walk_move(const WalkGraph &g, uint64_t nb, uint64_t x, int32_t &u, uint64_t &nb_next) {
-    const int64_t j = nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb));
-    if (g.arcs) {
-        const ulonglong2 a = g.arcs[j];
-        u = (int32_t)a.x;
-        nb_next = a.y;
-    } else {
-        u = g.col[j];
-        nb_next = (u != g.root) ? g.nbr[u] : 0ull;
-    }
-}
-
 // Returns the walk's length, or -1 if the time limit passed (p.err is set).
 static inline __device__ int64_t absorbed_walk(const WalkGraph &g, uint32_t tag, int64_t i, unsigned long long *y2,
                                         DevErr *err, uint64_t t0, uint64_t deadline) {
     const uint64_t c0 = (uint64_t)i | ((uint64_t)tag << 56);
     const uint64_t x0 = philox_w0(c0, 0, 0, g.qid, g.k0, g.k1);
     // a graph without edges is the single node v: the walk starts (and ends) there
-    int32_t u = g.root;
-    uint64_t nb = 0;
-    if (tag == 1) {
-        u = (int32_t)pick_below(x0, (uint64_t)g.n);
-        if (u != g.root) nb = g.nbr[u];
-    } else if (g.nnz > 0) {
-        u = g.col[pick_below(x0, (uint64_t)g.nnz)];
-        if (u != g.root) nb = g.nbr[u];
-    }
+    int32_t u = (tag == 1)      ? (int32_t)pick_below(x0, (uint64_t)g.n)
+                : (g.nnz > 0)   ? g.col[pick_below(x0, (uint64_t)g.nnz)]
+                                : g.root;
     int64_t len = 0;
+    if (g.arcs) {
+        // one dependent load per step: the arc gives the next node and its row
+        uint64_t nb = (u != g.root) ? g.nbr[u] : 0ull;
+        while (u != g.root) {
+            if (y2) atomicAdd(&y2[u], 1ull);
+            ++len;
+            const uint64_t x = philox_w0(c0, (uint64_t)len, 0, g.qid, g.k0, g.k1);
+            const ulonglong2 a = g.arcs[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
+            u = (int32_t)a.x;
+            nb = a.y;
+            if ((len & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
+                raise_err(err, kErrTimeout, 1);
+                return -1;
+            }
+        }
+        return len;
+    }
     while (u != g.root) {
+        const uint64_t nb = g.nbr[u];
         if (y2) atomicAdd(&y2[u], 1ull);
         ++len;
         const uint64_t x = philox_w0(c0, (uint64_t)len, 0, g.qid, g.k0, g.k1);
-        walk_move(g, nb, x, u, nb);
+        u = g.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
         if ((len & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
             raise_err(err, kErrTimeout, 1);
             return -1;
@@ -77,17 +75,26 @@ static inline __device__ bool query_walk(const WalkGraph &g, int32_t start, uint
                                   uint64_t deadline) {
     const uint64_t c0 = (uint64_t)i | (3ull << 56);
     int32_t u = start;
-    uint64_t nb = (u != g.root) ? g.nbr[u] : 0ull;
     int64_t da = 0, db = 0, steps = 0;
     double nl = 0.0;
+    uint64_t nb = (g.arcs && u != g.root) ? g.nbr[u] : 0ull;
     while (u != g.root) {
+        if (!g.arcs) nb = g.nbr[u];
         const uint32_t d = nbr_deg(nb);
         da += (u == a);
         db += (u == b);
         nl += 1.0 / (double)d;
         ++steps;
         const uint64_t x = philox_w0(c0, (uint64_t)steps, sub, g.qid, g.k0, g.k1);
-        walk_move(g, nb, x, u, nb);
+        const int64_t j = nbr_off(nb) + (int64_t)pick_below(x, d);
+        if (g.arcs) {
+            // one dependent load per step: the arc gives the next node and its row
+            const ulonglong2 r = g.arcs[j];
+            u = (int32_t)r.x;
+            nb = r.y;
+        } else {
+            u = g.col[j];
+        }
         if ((steps & 1023) == 0 && (wall_clock64() - t0 > deadline || err_set(err))) {
             raise_err(err, kErrTimeout, 2);
             return false;
