@@ -214,6 +214,33 @@ def bench_spantree(lap, g, root, omega):
             "lewalk_s_per_step_same_omega": lewalk_s, "spantree_over_lewalk_time": dt / lewalk_s}
 
 
+def bench_loop_paths(lap, g, root, omega):
+    """Loop-included paths (Sec. 3.4) on the mid workload: per Wilson sample,
+    the path from where absorbed walk i starts, read from the sample's
+    stacks, for both start laws; the fresh absorbed walks they stand in for
+    are timed beside them (their Wilson trees included)."""
+    out = {"workload": f"loop-included paths, Barabasi-Albert n=100000 m=5, omega={omega}"}
+    for tag, name in ((1, "uniform"), (2, "stationary")):
+        g.loop_included(omega, 1, tag, root, B=64)
+        lap.prof_reset()
+        lap.prof_enable(True)
+        t = time.perf_counter()
+        r = g.loop_included(omega, 1, tag, root, B=64)
+        dt = time.perf_counter() - t
+        lap.prof_enable(False)
+        ms, _ = lap.prof_read("loop_included")
+        out[name] = {"s": dt, "path_kernel_ms": ms, "path_steps": int(r["len"].sum()),
+                     "mean_len": float(r["len"].mean())}
+    g.sample_forests(omega, 1, root, y1=False, per_sample=False, y2=True, y2_pi=True, B=64)
+    lap.prof_reset()
+    lap.prof_enable(True)
+    g.sample_forests(omega, 1, root, y1=False, per_sample=False, y2=True, y2_pi=True, B=64)
+    lap.prof_enable(False)
+    ms_a, n_a = lap.prof_read("absorbed")
+    out["fresh_absorbed_kernel_ms_per_kind"] = ms_a / max(n_a, 1)
+    return out
+
+
 def bench_landmark(lap, gg):
     """Landmark study: Tr((I - P_v)^{-1}) for every node v of a
     Barabasi-Albert graph n = 10,000, m = 5 as the candidate root, 32 Wilson
@@ -394,6 +421,7 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-spantree", action="store_true")
     ap.add_argument("--no-landmark", action="store_true")
+    ap.add_argument("--no-loop-paths", action="store_true")
     ap.add_argument("--no-kc-families", action="store_true")
     ap.add_argument("--kc-n", type=int, default=100_000)
     ap.add_argument("--serve-queries", type=int, default=300)
@@ -507,6 +535,9 @@ def main():
     if not args.no_spantree:
         log("spantree")
         res["spantree"] = bench_spantree(lap, g, root, 1024)
+    if not args.no_loop_paths:
+        log("loop-included paths")
+        res["loop_paths"] = bench_loop_paths(lap, g, root, omega)
     if not args.no_landmark:
         log("landmark study")
         res["landmark"] = bench_landmark(lap, gg)
