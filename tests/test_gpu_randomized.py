@@ -1,0 +1,59 @@
+"""Randomised parity sweep: seeded random small graphs of several families,
+random roots, sample counts, seeds, stream and query ids, sampler forms,
+pools and scan rotations; every integer count must equal the oracle's.
+By Wilson's stack argument no schedule may change a count, so this also
+sweeps walker interleavings for races."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import csr, native
+from tests.gpu_common import both, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _graph(rng, i):
+    kind = i % 4
+    if kind == 0:
+        n = int(rng.integers(20, 400))
+        s, d, _ = gg.erdos_renyi_connected(n, float(rng.uniform(3.0, 9.0)) / n, int(rng.integers(1 << 30)))
+        return n, s, d, False
+    if kind == 1:
+        n = int(rng.integers(20, 3000))
+        s, d = gg.barabasi_albert(n, int(rng.integers(1, 5)), int(rng.integers(1 << 30)))
+        return n, s, d, False
+    if kind == 2:
+        r, c = int(rng.integers(2, 30)), int(rng.integers(2, 30))
+        s, d = gg.grid(r, c)
+        return r * c, s, d, False
+    scale = int(rng.integers(6, 12))
+    s, d = gg.rmat(scale, 8, seed=int(rng.integers(1 << 30)))
+    return 1 << scale, s, d, True
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_random_graph_counts_bit_exact(case):
+    rng = np.random.default_rng(1000 + case)
+    n, s, d, lcc = _graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=lcc)
+    root = int(rng.integers(0, og.n)) if case % 3 else csr.landmark(og)
+    omega = int(rng.integers(1, 300))
+    seed = int(rng.integers(1 << 62))
+    stream = int(rng.integers(0, 4))
+    qid = int(rng.integers(0, 1 << 40))
+    B = int(rng.integers(1, min(omega, 8) + 1))
+    mode, group = [(1, 0), (2, 0), (3, 2), (3, 4), (3, 8)][case % 5]
+    pool = int(rng.integers(0, 50))
+    sched = int(rng.integers(0, 1 << 31))
+    keep = sorted({0, omega - 1})
+    log(f"random case {case}: n={og.n} root={root} omega={omega} mode={mode}/{group} pool={pool}")
+    got = hg.sample_forests(omega, seed, root, y2=True, y2_pi=True, B=B, keep=keep, mode=mode, group=group,
+                            pool=pool, stream_id=stream, qid=qid, schedule=sched)
+    w = native.wilson(og, root, omega, seed, stream=stream, qid=qid, B=B, keep=keep)
+    a = native.absorbed(og, root, omega, seed, 1, stream=stream, qid=qid, B=B)
+    p = native.absorbed(og, root, omega, seed, 2, stream=stream, qid=qid, want_y2=False)
+    assert np.array_equal(got["Y1"], w["Y1"]) and np.array_equal(got["y1"], w["y1"])
+    assert np.array_equal(got["next"], w["next"]) and np.array_equal(got["draws"], w["draws"])
+    assert np.array_equal(got["Y2"], a["Y2"]) and np.array_equal(got["len_uniform"], a["len"])
+    assert np.array_equal(got["len_pi"], p["len"])
