@@ -145,3 +145,36 @@ def spantree_diag_blocks(X1b, X2b, omega, n):
     full = spantree_diag(X1b.sum(0), X2b.sum(0), omega, n)
     se = est.std(axis=0, ddof=1) / math.sqrt(B) if B > 1 else np.full(n, np.nan)
     return full, se
+
+
+def pair_entries(V, omega, d_s, d_t):
+    """Entries of L_v^{-1} and resistances from loop-included path counts
+    (Sec. 3.4; r(s,t) of Sec. 2 through the grounded inverse).
+
+    V: int64 [B][n_pairs][4] per-block departures (s on the path from s, t on
+    the path from s, t on the path from t, s on the path from t); d_s, d_t:
+    degrees.  Returns a dict of FP64 arrays over pairs:
+      lv_ss = sum V0 / (omega d_s), lv_tt = sum V2 / (omega d_t),
+      lv_st = (sum V1 / d_t + sum V3 / d_s) / (2 omega)   (both orders of the
+              symmetric entry),
+      r     = (sum V0 / d_s - sum V1 / d_t + sum V2 / d_t - sum V3 / d_s) / omega,
+      r_se  = batch-means standard error of r over the B blocks.
+    """
+    V = np.asarray(V, np.int64)
+    B = V.shape[0]
+    d_s = np.asarray(d_s, np.float64)
+    d_t = np.asarray(d_t, np.float64)
+    tot = V.sum(0).astype(np.float64)
+
+    def r_of(a, m):
+        return (a[..., 0] / d_s - a[..., 1] / d_t + a[..., 2] / d_t - a[..., 3] / d_s) / m
+
+    out = dict(lv_ss=tot[:, 0] / (omega * d_s), lv_tt=tot[:, 2] / (omega * d_t),
+               lv_st=(tot[:, 1] / d_t + tot[:, 3] / d_s) / (2.0 * omega), r=r_of(tot, omega))
+    if B > 1:
+        sizes = block_sizes(omega, B).astype(np.float64)
+        rb = np.stack([r_of(V[b].astype(np.float64), sizes[b]) for b in range(B)])
+        out["r_se"] = rb.std(axis=0, ddof=1) / math.sqrt(B)
+    else:
+        out["r_se"] = np.full(V.shape[1], np.nan)
+    return out

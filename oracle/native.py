@@ -57,6 +57,8 @@ def lib():
         L.oracle_query_walks.restype = i32
         L.oracle_loop_included.argtypes = [i64, P, P, i32, u64, u32, u64, i32, i64, i64, i64, i32, P, P, i32]
         L.oracle_loop_included.restype = i32
+        L.oracle_pair_paths.argtypes = [i64, P, P, i32, u64, u32, u64, i64, i64, i64, i32, i64, P, P, P, i32]
+        L.oracle_pair_paths.restype = i32
         L.oracle_bfs_tree.argtypes = [i64, P, P, i32, P]
         L.oracle_bfs_tree.restype = i64
         L.oracle_spantree_tree.argtypes = [i64, P, i32, P, P, P, P, P, P, P]
@@ -253,3 +255,23 @@ def loop_included(g, root, n_paths, seed, tag, *, stream=0, qid=0, sample_begin=
     if st != 0:
         raise MemoryError("oracle_loop_included failed")
     return dict(Y2=Y2, len=ln)
+
+
+def pair_paths(g, root, n_samples, seed, s, t, *, stream=0, qid=0, sample_begin=0, omega_total=None, B=1,
+               threads=0):
+    """Loop-included paths from s_j and from t_j through the stacks of each
+    Wilson sample: V [B][n_pairs][4] = departures (from s on the path from s,
+    from t on the path from s, from t on the path from t, from s on the path
+    from t)."""
+    n, rp, col = _graph(g)
+    if omega_total is None:
+        omega_total = sample_begin + n_samples
+    s = np.ascontiguousarray(s, np.int32)
+    t = np.ascontiguousarray(t, np.int32)
+    assert s.shape == t.shape
+    V = np.zeros((B, len(s), 4), np.int64)
+    st = lib().oracle_pair_paths(n, _p(rp), _p(col), int(root), seed, stream, qid, sample_begin, n_samples,
+                                 omega_total, B, len(s), _p(s), _p(t), _p(V), threads)
+    if st != 0:
+        raise MemoryError("oracle_pair_paths failed")
+    return V

@@ -12,6 +12,8 @@
  *   - v-absorbed walks from a uniform start (Alg. 2, second phase) or from a
  *     start drawn from the stationary distribution (Alg. 4);
  *   - loop-included paths read from the stacks (Sec. 3.4, Fig. 1(d)).
+ *   - loop-included paths from given node pairs, the counts behind entries of
+ *     L_v^{-1} and effective resistances (Sec. 3.4, Sec. 2).
  * Random choices (the paper leaves the generator open):
  *   - generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11);
  *   - key = (seed, stream<<32 | root);
@@ -607,6 +609,90 @@ int32_t oracle_loop_included(int64_t n, const int64_t *rp, const int32_t *col, i
                 }
                 for (int64_t t = 0; t < nt; ++t) pos[touched[t]] = 0;
                 if (len_per_path) len_per_path[q] = len;
+            }
+        }
+        free(pos); free(touched);
+    }
+    return status;
+}
+
+/* ------------------------------------------------------------ node pairs */
+/*
+ * Loop-included paths from given nodes (Sec. 3.4, the loop-erased-walk
+ * interpretation of L_v^{-1}): (L_v^{-1})_su is the expected number of times
+ * u occurs (u != v) on the path from s through the stacks of one Wilson
+ * sample, divided by d_u.  With that, the resistance of Sec. 2 is
+ * r(s,t) = (L_v^{-1})_ss + (L_v^{-1})_tt - 2 (L_v^{-1})_st (grounding at v
+ * leaves resistances unchanged; row and column v of the grounded inverse are
+ * zero).
+ *
+ * For sample i in [sample_begin, sample_begin + n_samples) and pair j the path
+ * from s_j and the path from t_j are run through the stacks of sample i, each
+ * with its own departure counts starting at zero, so each is distributed as a
+ * v-absorbed walk from its start.  Block b = floor(i*B/omega_total) of
+ * V ([B][n_pairs][4]) gets:
+ *   [0] departures from s_j on the path from s_j,
+ *   [1] departures from t_j on the path from s_j,
+ *   [2] departures from t_j on the path from t_j,
+ *   [3] departures from s_j on the path from t_j.
+ */
+int32_t oracle_pair_paths(int64_t n, const int64_t *rp, const int32_t *col, int32_t root,
+                          uint64_t seed, uint32_t stream, uint64_t qid,
+                          int64_t sample_begin, int64_t n_samples, int64_t omega_total, int32_t B,
+                          int64_t n_pairs, const int32_t *s, const int32_t *t, int64_t *V,
+                          int32_t n_threads) {
+    if (B < 1) B = 1;
+    const uint64_t k0 = seed, k1 = make_key1(stream, root);
+    int32_t status = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        int64_t *pos = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+        int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!pos || !touched) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            status = -1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+            for (int64_t q = 0; q < n_samples; ++q) {
+                const int64_t i = sample_begin + q;
+                const int64_t b = (int64_t)(((__int128)i * B) / omega_total);
+                draw_ctx dc;
+                memset(&dc, 0, sizeof dc);
+                dc.rp = rp; dc.col = col; dc.k0 = k0; dc.k1 = k1; dc.c0 = (uint64_t)i; dc.qid = qid;
+                for (int64_t j = 0; j < n_pairs; ++j) {
+                    for (int side = 0; side < 2; ++side) {
+                        const int32_t from = side ? t[j] : s[j];
+                        const int32_t other = side ? s[j] : t[j];
+                        int64_t nt = 0;
+                        int32_t u = from;
+                        while (u != root) {
+                            if (pos[u] == 0) touched[nt++] = u;
+                            const int32_t w = stack_entry(&dc, u, pos[u]);
+                            pos[u] += 1;
+                            u = w;
+                        }
+                        /* departures from the start node and from the other node */
+                        const int64_t here = (from == root) ? 0 : pos[from];
+                        const int64_t there = (other == root) ? 0 : pos[other];
+                        int64_t *row = V + (b * n_pairs + j) * 4;
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                        row[side ? 2 : 0] += here;
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                        row[side ? 3 : 1] += there;
+                        for (int64_t k = 0; k < nt; ++k) pos[touched[k]] = 0;
+                    }
+                }
             }
         }
         free(pos); free(touched);
