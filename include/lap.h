@@ -312,6 +312,39 @@ int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, double *diag, 
 int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t tag, int64_t *Y2, int64_t *len,
                       void *hip_stream);
 
+/*
+ * lap_pair_paths -- entries of L_v^{-1} and effective resistances of node
+ * pairs from loop-included paths of the Wilson stacks (Sec. 3.4, the
+ * loop-erased-walk interpretation of L_v^{-1}; r(s,t) of Sec. 2, unchanged by
+ * grounding at v).  For every sample i of a and pair j, the path from s_j
+ * and the path from t_j through the stacks of sample i, each taking at its
+ * c-th departure from u the entry S_i[u][c] (Philox counter (i, u, c, qid):
+ * the sampler's own draws), until they reach v.  The departures from u of the
+ * path from s, divided by d_u, estimate (L_v^{-1})_su.
+ *   ps, pt  [n_pairs] node ids (host), 1 <= n_pairs <= 2^30; a node may be v
+ *           (its row of the grounded inverse is zero) and s == t is allowed.
+ *   check   1: run the Wilson samples too and fail with LAP_EDEVICE if a path
+ *           ever uses an entry the sampler did not draw (c >= k_u; by the
+ *           order independence of the stacks this never happens);
+ *           0: read the same entries without running the sampler (identical
+ *           results, no Wilson work).
+ * Outputs (host unless LAP_OUT_DEVICE; any may be NULL):
+ *   V     int64 [B][n_pairs][4] per sample block: departures from s on the
+ *         path from s, from t on the path from s, from t on the path from t,
+ *         from s on the path from t (exact);
+ *   r     [n_pairs] (V0/d_s - V1/d_t + V2/d_t - V3/d_s) / omega over all blocks;
+ *   r_se  [n_pairs] batch-means standard error of r (NaN when B == 1);
+ *   lv    [n_pairs][3] (L_v^{-1})_ss, (L_v^{-1})_st, (L_v^{-1})_tt with
+ *         the off-diagonal entry averaged over both orders:
+ *         V0/(omega d_s), (V1/d_t + V3/d_s)/(2 omega), V2/(omega d_t).
+ * Scratch: 8 bytes per node per lane in flight (at most 32 GiB), plus the
+ * Wilson state when check is 1.  Walk steps are reported by lap_last_stats
+ * as absorbed steps.
+ */
+int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int32_t *ps, const int32_t *pt,
+                   int64_t n_pairs, int32_t check, int64_t *V, double *r, double *r_se, double *lv,
+                   void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /*
@@ -408,7 +441,8 @@ const char *lap_last_error(void);
  * bracketed by HIP events on the stream it runs on; lap_prof_read returns
  * the accumulated milliseconds and launch count for a kernel name
  * ("wilson_wave", "wilson_lane", "wilson_group", "spantree", "loop_included",
- * "absorbed", "assemble", "batch", "batch_assemble").  Returns
+ * "pair_paths", "pair_assemble", "absorbed", "assemble", "batch",
+ * "batch_assemble").  Returns
  * LAP_EINVAL for an unknown name. */
 int lap_prof_enable(int on);
 int lap_prof_reset(void);

@@ -697,6 +697,122 @@ extern "C" int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t
     return LAP_OK;
 }
 
+// ------------------------------------------- loop-included paths, node pairs
+extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int32_t *ps, const int32_t *pt,
+                              int64_t n_pairs, int32_t check, int64_t *V, double *r_out, double *r_se,
+                              double *lv, void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (n_pairs < 1 || n_pairs > ((int64_t)1 << 30)) return fail(LAP_EINVAL, "n_pairs must be in [1, 2^30]");
+    if (!ps || !pt) return fail(LAP_EINVAL, "pair arrays are NULL");
+    if (check != 0 && check != 1) return fail(LAP_EINVAL, "check must be 0 or 1");
+    Resolved r;
+    int rc = resolve_args(g, a, 0, nullptr, r);
+    if (rc != LAP_OK) return rc;
+    const int64_t n = g->csr.n;
+    for (int64_t j = 0; j < n_pairs; ++j)
+        if (ps[j] < 0 || ps[j] >= n || pt[j] < 0 || pt[j] >= n) return fail(LAP_EINVAL, "pair node out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Timer tm;
+    // lanes in flight: each owns n 8-byte counters; at most 32 GiB of them and
+    // no more than the work has paths
+    const int64_t paths = 2 * n_pairs;
+    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)32 << 30) / (8 * std::max<int64_t>(n, 1)));
+    const int64_t max_lanes = std::min<int64_t>({by_mem, (int64_t)1 << 17, r.omega * paths});
+    const size_t vwords = (size_t)r.B * n_pairs * 4;
+    if (g->pair_cnt.ensure(sizeof(uint64_t) * (size_t)max_lanes * n + 8) ||
+        g->pair_ids.ensure(sizeof(int32_t) * (size_t)paths) || g->pair_v.ensure(sizeof(uint64_t) * vwords) ||
+        g->pair_out.ensure(sizeof(double) * (size_t)n_pairs * 5) || g->err.ensure(sizeof(DevErr)) ||
+        g->stats.ensure(sizeof(uint64_t) * kNumStats))
+        return fail(LAP_ENOMEM, "cannot allocate pair path workspace");
+    int32_t *d_ids = g->pair_ids.as<int32_t>();
+    HIP_TRY(hipMemcpyAsync(d_ids, ps, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_ids + n_pairs, pt, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u64(g->pair_v.as<uint64_t>(), 0ull, (int64_t)vwords, s));
+    HIP_TRY(launch_fill_u64(g->pair_cnt.as<uint64_t>(), 0ull, max_lanes * n, s));
+    const double tmo = a->timeout_s > 0 ? a->timeout_s : 120.0;
+    int64_t acc[kNumStats] = {0};
+    uint64_t tag_next = 1;
+    for (int64_t done = 0; done < r.omega;) {
+        // samples of this launch, and lanes per sample
+        int64_t chunk = check ? std::min({r.slots, r.omega - done, max_lanes}) : std::min(r.omega - done, max_lanes);
+        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(paths, max_lanes / chunk));
+        const int64_t per_lane = (paths + K - 1) / K;
+        if (tag_next + (uint64_t)per_lane >= ((uint64_t)1 << 32)) {
+            HIP_TRY(launch_fill_u64(g->pair_cnt.as<uint64_t>(), 0ull, max_lanes * n, s));
+            tag_next = 1;
+        }
+        PairParams p;
+        std::memset(&p, 0, sizeof p);
+        if (check) {
+            Resolved rr = r;
+            rr.omega = chunk;
+            rr.begin = r.begin + done;
+            rr.slots = chunk;
+            rr.wilson = true;
+            rr.y2u = rr.y2p = false;
+            RunOut o;
+            if ((rc = run_sampling(g, rr, a, 0, nullptr, false, false, o, s, tm)) != LAP_OK) return rc;
+            p.state = g->state.as<uint64_t>();
+            p.slot_epoch = g->epoch.as<uint32_t>();
+        } else {
+            HIP_TRY(launch_fill_u64(g->err.as<uint64_t>(), 0ull, 1, s));
+            HIP_TRY(launch_fill_u64(g->stats.as<uint64_t>(), 0ull, kNumStats, s));
+        }
+        p.n = n;
+        p.nbr = g->nbr.as<uint64_t>();
+        p.col = g->col.as<int32_t>();
+        p.root = r.root;
+        p.k0 = a->seed;
+        p.k1 = ((uint64_t)a->stream << 32) | (uint64_t)(uint32_t)r.root;
+        p.qid = a->qid;
+        p.ps = d_ids;
+        p.pt = d_ids + n_pairs;
+        p.n_pairs = n_pairs;
+        p.cnt = g->pair_cnt.as<uint64_t>();
+        p.n_lanes = chunk * K;
+        p.lanes_per_sample = (int32_t)K;
+        p.tag_base = (uint32_t)tag_next;
+        p.sample_begin = r.begin + done;
+        p.n_total = r.total;
+        p.n_blocks = r.B;
+        p.V = g->pair_v.as<unsigned long long>();
+        p.stats = g->stats.as<unsigned long long>();
+        p.err = g->err.as<DevErr>();
+        p.deadline = (uint64_t)(tmo * g->clock_khz * 1000.0);
+        tm.begin("pair_paths", s);
+        HIP_TRY(launch_pair_paths(p, s));
+        tm.end(s);
+        if ((rc = finish(g, s, tm)) != LAP_OK) return rc;
+        for (int i = 0; i < kNumStats; ++i) acc[i] += g->last_stats[i];
+        tag_next += (uint64_t)per_lane;
+        done += chunk;
+    }
+    for (int i = 0; i < kNumStats; ++i) g->last_stats[i] = acc[i];
+    double *d = g->pair_out.as<double>();
+    PairAsmParams q;
+    q.nbr = g->nbr.as<uint64_t>();
+    q.ps = d_ids;
+    q.pt = d_ids + n_pairs;
+    q.n_pairs = n_pairs;
+    q.omega = r.omega;
+    q.B = r.B;
+    q.V = g->pair_v.as<unsigned long long>();
+    q.r = d;
+    q.r_se = d + n_pairs;
+    q.lv = d + 2 * n_pairs;
+    tm.begin("pair_assemble", s);
+    HIP_TRY(launch_pair_assemble(q, s));
+    tm.end(s);
+    if ((rc = copy_out(V, g->pair_v.ptr, sizeof(int64_t) * vwords, s)) ||
+        (rc = copy_out(r_out, d, sizeof(double) * n_pairs, s)) ||
+        (rc = copy_out(r_se, d + n_pairs, sizeof(double) * n_pairs, s)) ||
+        (rc = copy_out(lv, d + 2 * n_pairs, sizeof(double) * 3 * n_pairs, s)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    tm.collect();
+    return LAP_OK;
+}
+
 static lap_sample_args default_args(int32_t root, int64_t omega, uint64_t seed, int32_t B) {
     lap_sample_args a;
     std::memset(&a, 0, sizeof a);

@@ -1,6 +1,6 @@
 // Parameter blocks of the kernels beyond the Wilson samplers: the batched
-// launch, the serving launch, the SpanTree pass, the loop-included paths and
-// the SpanTree assembly.
+// launch, the serving launch, the SpanTree pass, the loop-included paths (from
+// absorbed-walk starts and from node pairs) and the SpanTree assembly.
 #pragma once
 
 #include "lap_device.h"
@@ -108,6 +108,38 @@ struct LoopParams {
     int64_t *len_out;              // [n_paths] of this launch, or null
     DevErr *err;
     uint64_t deadline;
+};
+
+// Loop-included paths from node pairs over the stacks of the launch's samples (loops.hip)
+struct PairParams {
+    int64_t n;
+    const uint64_t *nbr;
+    const int32_t *col;
+    int32_t root;
+    uint64_t k0, k1, qid;
+    const uint64_t *state;         // [samples][n] Wilson trees of the launch's samples, or null (no check)
+    const uint32_t *slot_epoch;    // [samples], with state
+    const int32_t *ps, *pt;        // [n_pairs]
+    int64_t n_pairs;
+    uint64_t *cnt;                 // [n_lanes][n] departures of the lane's current path: tag << 32 | count
+    int64_t n_lanes;               // samples of the launch * lanes_per_sample
+    int32_t lanes_per_sample;
+    uint32_t tag_base;             // tag of each lane's first path in this launch (tags are never 0)
+    int64_t sample_begin, n_total;
+    int32_t n_blocks;
+    unsigned long long *V;         // [B][n_pairs][4]
+    unsigned long long *stats;
+    DevErr *err;
+    uint64_t deadline;
+};
+
+struct PairAsmParams {
+    const uint64_t *nbr;
+    const int32_t *ps, *pt;
+    int64_t n_pairs, omega;
+    int32_t B;
+    const unsigned long long *V;   // [B][n_pairs][4]
+    double *r, *r_se, *lv;         // [n_pairs], [n_pairs], [n_pairs][3]; any may be null
 };
 
 struct SpanAsmParams {

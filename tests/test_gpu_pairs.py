@@ -1,0 +1,110 @@
+"""Loop-included paths from node pairs on the GPU against the oracle: the
+per-block departure sums V are bit-exact (the same stack entries are read),
+with and without the Wilson run that checks every entry was drawn, in every
+sampler form; the FP64 entries and resistances agree to 1e-12 and sit within
+their standard errors of the dense truth."""
+import numpy as np
+import pytest
+
+from oracle import csr, dense, estimators, native
+from tests.gpu_common import ba_edges, both, er256_edges, log, small_cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _pairs(n, root, k, seed):
+    rng = np.random.default_rng(seed)
+    s = rng.integers(0, n, k).astype(np.int32)
+    t = rng.integers(0, n, k).astype(np.int32)
+    s[0], t[0] = root, t[0]            # a pair with the root
+    if k > 1:
+        t[1] = s[1]                    # an equal pair
+    return s, t
+
+
+def _same(og, got, s, t, omega, seed, B, root, sample_begin=0, n_total=None):
+    exp = native.pair_paths(og, root, omega, seed, s, t, B=B, sample_begin=sample_begin, omega_total=n_total)
+    assert np.array_equal(got["V"], exp)
+    e = estimators.pair_entries(exp, omega, og.deg[s], og.deg[t])
+    np.testing.assert_allclose(got["r"], e["r"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(got["lv"], np.stack([e["lv_ss"], e["lv_st"], e["lv_tt"]], axis=1),
+                               rtol=1e-12, atol=1e-15)
+    if B > 1:
+        np.testing.assert_allclose(got["r_se"], e["r_se"], rtol=1e-9, atol=1e-15)
+    else:
+        assert np.isnan(got["r_se"]).all()
+
+
+@pytest.mark.parametrize("mode,group", [(2, 0), (3, 4), (1, 0)])
+def test_pair_paths_small_graphs_bit_exact(mode, group):
+    for name, n, src, dst in small_cases():
+        og, hg = both(n, src, dst)
+        for root in sorted({0, csr.landmark(og), og.n - 1}):
+            s, t = _pairs(og.n, root, 9, root + 1)
+            for check in (1, 0):
+                log(f"pairs {name} root {root} mode {mode} check {check}")
+                got = hg.pair_paths(s, t, 120, 4, root, B=3, check=check, mode=mode, group=group, pool=7)
+                _same(og, got, s, t, 120, 4, 3, root)
+
+
+def test_pair_paths_er256_workload_bit_exact_and_against_dense():
+    n, src, dst = er256_edges()
+    og, hg = both(n, src, dst)
+    root = csr.landmark(og)
+    s, t = _pairs(og.n, root, 256, 5)
+    omega, B = 1 << 14, 64
+    for check in (1, 0):
+        log(f"pairs er256 check {check}")
+        got = hg.pair_paths(s, t, omega, 1, root, B=B, check=check)
+        _same(og, got, s, t, omega, 1, B, root)
+    Ld = dense.pinv_eigh(dense.laplacian(og))
+    truth = np.array([dense.resistance(Ld, a, b) for a, b in zip(s, t)])
+    ok = got["r_se"] > 0
+    z = (got["r"][ok] - truth[ok]) / got["r_se"][ok]
+    assert np.abs(z).max() < 4.7 and (np.abs(z) < 3).mean() > 0.97
+    np.testing.assert_allclose(got["r"][~ok], truth[~ok], atol=1e-12)
+
+
+def test_pair_paths_mid_workload_bit_exact():
+    """Barabasi-Albert n = 100,000, m = 5, root = max degree: 64 pairs over
+    256 samples, with the Wilson check and without."""
+    n, src, dst = ba_edges(100_000, 5, 0)
+    og, hg = both(n, src, dst)
+    root = csr.landmark(og)
+    s, t = _pairs(og.n, root, 64, 6)
+    for check in (1, 0):
+        log(f"pairs ba100k check {check}")
+        got = hg.pair_paths(s, t, 256, 1, root, B=8, check=check)
+        _same(og, got, s, t, 256, 1, 8, root)
+
+
+def test_pair_paths_many_pairs_few_samples_and_resume():
+    """More paths than samples (several lanes per sample), and a run split
+    in two sample ranges."""
+    n, src, dst = ba_edges(5000, 3, 1)
+    og, hg = both(n, src, dst)
+    root = csr.landmark(og)
+    s, t = _pairs(og.n, root, 3000, 7)
+    log("pairs ba5k many pairs")
+    got = hg.pair_paths(s, t, 3, 2, root, check=1)
+    _same(og, got, s, t, 3, 2, 1, root)
+    s, t = s[:50], t[:50]
+    full = hg.pair_paths(s, t, 40, 2, root, B=4, pool=6)
+    a = hg.pair_paths(s, t, 15, 2, root, B=4, sample_begin=0, n_total=40, check=0)
+    b = hg.pair_paths(s, t, 25, 2, root, B=4, sample_begin=15, n_total=40, mode=3, group=2)
+    assert np.array_equal(a["V"] + b["V"], full["V"])
+    _same(og, full, s, t, 40, 2, 4, root)
+
+
+def test_pair_paths_argument_errors():
+    from paper_2311_10290_amd import LapError
+    n, src, dst = er256_edges()
+    _, hg = both(n, src, dst)
+    with pytest.raises(LapError):
+        hg.pair_paths([], [], 10, 1)
+    with pytest.raises(LapError):
+        hg.pair_paths([0, 300], [1, 2], 10, 1)
+    with pytest.raises(LapError):
+        hg.pair_paths([0], [-1], 10, 1)
+    with pytest.raises(ValueError):
+        hg.pair_paths([0, 1], [1], 10, 1)
