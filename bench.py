@@ -241,6 +241,35 @@ def bench_loop_paths(lap, g, root, omega):
     return out
 
 
+def bench_pairs(lap, g, root, n, omega=1024, n_pairs=256):
+    """Resistances and grounded-inverse entries of node pairs from
+    loop-included paths (Sec. 3.4) on the mid workload: 256 random pairs
+    (seed 3), 1024 samples, B = 64; the entries read without the sampler
+    (check 0), then with the Wilson run that checks them (check 1)."""
+    rng = np.random.default_rng(3)
+    s = rng.integers(0, n, n_pairs).astype(np.int32)
+    t = rng.integers(0, n, n_pairs).astype(np.int32)
+    out = {"workload": f"node pairs, Barabasi-Albert n=100000 m=5, {n_pairs} random pairs, omega={omega}",
+           "paths": 2 * n_pairs * omega}
+    for check in (0, 1):
+        g.pair_paths(s, t, omega, 1, root, B=64, check=check)
+        lap.prof_reset()
+        lap.prof_enable(True)
+        t0 = time.perf_counter()
+        r = g.pair_paths(s, t, omega, 1, root, B=64, check=check)
+        dt = time.perf_counter() - t0
+        lap.prof_enable(False)
+        ms, _ = lap.prof_read("pair_paths")
+        st = g.last_stats()
+        out[f"check{check}"] = {"s": dt, "path_kernel_ms": ms, "path_steps": st["absorbed_steps"],
+                                "wilson_steps": st["wilson_steps"],
+                                "path_steps_per_s": st["absorbed_steps"] / (ms * 1e-3)}
+    ok = r["r"] > 0
+    out["median_rel_se_r"] = float(np.median(r["r_se"][ok] / r["r"][ok]))
+    out["mean_path_len"] = out["check0"]["path_steps"] / out["paths"]
+    return out
+
+
 def bench_landmark(lap, gg):
     """Landmark study: Tr((I - P_v)^{-1}) for every node v of a
     Barabasi-Albert graph n = 10,000, m = 5 as the candidate root, 32 Wilson
@@ -422,6 +451,7 @@ def main():
     ap.add_argument("--no-spantree", action="store_true")
     ap.add_argument("--no-landmark", action="store_true")
     ap.add_argument("--no-loop-paths", action="store_true")
+    ap.add_argument("--no-pairs", action="store_true")
     ap.add_argument("--no-kc-families", action="store_true")
     ap.add_argument("--kc-n", type=int, default=100_000)
     ap.add_argument("--serve-queries", type=int, default=300)
@@ -538,6 +568,9 @@ def main():
     if not args.no_loop_paths:
         log("loop-included paths")
         res["loop_paths"] = bench_loop_paths(lap, g, root, omega)
+    if not args.no_pairs:
+        log("node-pair paths")
+        res["pairs"] = bench_pairs(lap, g, root, n)
     if not args.no_landmark:
         log("landmark study")
         res["landmark"] = bench_landmark(lap, gg)

@@ -120,7 +120,7 @@ def declare(lib):
         "lap_spantree": ([P, ctypes.POINTER(SampleArgs), P, P, P, P, P], i32),
         "lap_spantree_estimate": ([P, ctypes.POINTER(SampleArgs), P, P, P, P, P, P], i32),
         "lap_loop_included": ([P, ctypes.POINTER(SampleArgs), i32, P, P, P], i32),
-        "lap_pair_paths": ([P, ctypes.POINTER(SampleArgs), P, P, i64, i32, P, P, P, P, P], i32),
+        "lap_pair_paths": ([P, ctypes.POINTER(SampleArgs), P, P, i64, i32, i64, P, P, P, P, P], i32),
         "lap_server_create": ([P, ctypes.POINTER(ServerConfig), P, P], i32),
         "lap_server_submit": ([P, ctypes.POINTER(Query)], i32),
         "lap_server_step": ([P, i32], i32),

@@ -208,8 +208,8 @@ class Graph:
                                                 _ptr(out["len"]), _stream(stream)))
         return out
 
-    def pair_paths(self, s, t, omega, seed, root=-1, *, B=1, check=True, sample_begin=0, n_total=0, mode=0,
-                   pool=0, group=0, stream_id=0, qid=0, timeout_s=0.0, stream=None):
+    def pair_paths(self, s, t, omega, seed, root=-1, *, B=1, check=True, lanes=0, sample_begin=0, n_total=0,
+                   mode=0, pool=0, group=0, stream_id=0, qid=0, timeout_s=0.0, stream=None):
         """Loop-included paths from node pairs (lap_pair_paths): V [B][n_pairs][4],
         r and r_se [n_pairs], lv [n_pairs][3]."""
         s = np.ascontiguousarray(s, np.int32)
@@ -221,7 +221,7 @@ class Graph:
         P = len(s)
         out = dict(V=np.zeros((B, P, 4), np.int64), r=np.zeros(P), r_se=np.zeros(P), lv=np.zeros((P, 3)))
         _check(load_library().lap_pair_paths(self._h, ctypes.byref(a), _ptr(s), _ptr(t), P, int(bool(check)),
-                                             _ptr(out["V"]), _ptr(out["r"]), _ptr(out["r_se"]), _ptr(out["lv"]),
+                                             int(lanes), _ptr(out["V"]), _ptr(out["r"]), _ptr(out["r_se"]), _ptr(out["lv"]),
                                              _stream(stream)))
         return out
 

@@ -698,13 +698,37 @@ extern "C" int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t
 }
 
 // ------------------------------------------- loop-included paths, node pairs
+namespace {
+
+constexpr int32_t kPairHashLog2 = 14;              // 16384-word table per lane (128 KiB)
+constexpr int64_t kPairMaxLanes = (int64_t)1 << 17;
+constexpr int64_t kPairMaxPairs = (int64_t)1 << 23;
+constexpr int64_t kPairCountBudget = (int64_t)32 << 30;   // bytes of departure counters per form
+
+// Count words and last tags for `lanes` lanes of `words` words each; lanes
+// beyond those already set up (all of them after a reallocation) start zeroed.
+int ready_lanes(DevBuf &words_buf, DevBuf &tags_buf, int64_t &ready, int64_t lanes, int64_t words,
+                hipStream_t s) {
+    if (lanes <= ready) return LAP_OK;
+    if (words_buf.ensure(sizeof(uint64_t) * (size_t)lanes * words + 8) ||
+        tags_buf.ensure(sizeof(uint32_t) * (size_t)lanes + 8))
+        return fail(LAP_ENOMEM, "cannot allocate pair path counters");
+    HIP_TRY(launch_fill_u64(words_buf.as<uint64_t>(), 0ull, lanes * words, s));
+    HIP_TRY(launch_fill_u64(tags_buf.as<uint64_t>(), 0ull, (lanes + 1) / 2, s));
+    ready = lanes;
+    return LAP_OK;
+}
+
+}  // namespace
+
 extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int32_t *ps, const int32_t *pt,
-                              int64_t n_pairs, int32_t check, int64_t *V, double *r_out, double *r_se,
-                              double *lv, void *hip_stream) {
+                              int64_t n_pairs, int32_t check, int64_t lanes, int64_t *V, double *r_out,
+                              double *r_se, double *lv, void *hip_stream) {
     if (!g) return fail(LAP_EINVAL, "graph is NULL");
-    if (n_pairs < 1 || n_pairs > ((int64_t)1 << 30)) return fail(LAP_EINVAL, "n_pairs must be in [1, 2^30]");
+    if (n_pairs < 1 || n_pairs > kPairMaxPairs) return fail(LAP_EINVAL, "n_pairs must be in [1, 2^23]");
     if (!ps || !pt) return fail(LAP_EINVAL, "pair arrays are NULL");
     if (check != 0 && check != 1) return fail(LAP_EINVAL, "check must be 0 or 1");
+    if (lanes < 0) return fail(LAP_EINVAL, "lanes must be >= 0");
     Resolved r;
     int rc = resolve_args(g, a, 0, nullptr, r);
     if (rc != LAP_OK) return rc;
@@ -713,34 +737,49 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
         if (ps[j] < 0 || ps[j] >= n || pt[j] < 0 || pt[j] >= n) return fail(LAP_EINVAL, "pair node out of range");
     hipStream_t s = (hipStream_t)hip_stream;
     Timer tm;
-    // lanes in flight: each owns n 8-byte counters; at most 32 GiB of them and
-    // no more than the work has paths
     const int64_t paths = 2 * n_pairs;
-    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)32 << 30) / (8 * std::max<int64_t>(n, 1)));
-    const int64_t max_lanes = std::min<int64_t>({by_mem, (int64_t)1 << 17, r.omega * paths});
+    const int64_t hash_words = (int64_t)1 << kPairHashLog2;
+    // Lanes in flight: bounded by the counter budget and by `lanes`.  Graphs
+    // with more nodes than a table has words use the hashed form first.
+    auto lane_cap = [&](int64_t words) {
+        int64_t c = std::min<int64_t>(kPairCountBudget / (8 * words), kPairMaxLanes);
+        if (lanes > 0) c = std::min(c, lanes);
+        return std::max<int64_t>(c, 1);
+    };
+    const int64_t dense_cap = lane_cap(std::max<int64_t>(n, 1));
+    const int64_t hash_cap = lane_cap(hash_words);
+    bool hashed = n > hash_words;
     const size_t vwords = (size_t)r.B * n_pairs * 4;
-    if (g->pair_cnt.ensure(sizeof(uint64_t) * (size_t)max_lanes * n + 8) ||
-        g->pair_ids.ensure(sizeof(int32_t) * (size_t)paths) || g->pair_v.ensure(sizeof(uint64_t) * vwords) ||
-        g->pair_out.ensure(sizeof(double) * (size_t)n_pairs * 5) || g->err.ensure(sizeof(DevErr)) ||
-        g->stats.ensure(sizeof(uint64_t) * kNumStats))
+    if (g->pair_ids.ensure(sizeof(int32_t) * (size_t)paths) || g->pair_v.ensure(sizeof(uint64_t) * vwords) ||
+        g->pair_out.ensure(sizeof(double) * (size_t)n_pairs * 5) || g->pair_next.ensure(sizeof(uint64_t) * 128) ||
+        g->err.ensure(sizeof(DevErr)) || g->stats.ensure(sizeof(uint64_t) * kNumStats))
         return fail(LAP_ENOMEM, "cannot allocate pair path workspace");
     int32_t *d_ids = g->pair_ids.as<int32_t>();
     HIP_TRY(hipMemcpyAsync(d_ids, ps, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_ids + n_pairs, pt, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_fill_u64(g->pair_v.as<uint64_t>(), 0ull, (int64_t)vwords, s));
-    HIP_TRY(launch_fill_u64(g->pair_cnt.as<uint64_t>(), 0ull, max_lanes * n, s));
     const double tmo = a->timeout_s > 0 ? a->timeout_s : 120.0;
     int64_t acc[kNumStats] = {0};
-    uint64_t tag_next = 1;
+    int64_t queued_total = 0, hashed_items = 0;
+    auto run = [&](PairParams &p, bool hash_form, int64_t L) -> int {
+        p.n_lanes = L;
+        p.n_parts = (int32_t)std::min<int64_t>(8, (L + 63) / 64);
+        HIP_TRY(launch_fill_u64(g->pair_next.as<uint64_t>(), 0ull, 128, s));
+        tm.begin("pair_paths", s);
+        HIP_TRY(launch_pair_paths(p, hash_form, s));
+        tm.end(s);
+        int rc2 = finish(g, s, tm);
+        if (rc2 != LAP_OK) return rc2;
+        for (int k = 0; k < kNumStats; ++k) acc[k] += g->last_stats[k];
+        return LAP_OK;
+    };
     for (int64_t done = 0; done < r.omega;) {
-        // samples of this launch, and lanes per sample
-        int64_t chunk = check ? std::min({r.slots, r.omega - done, max_lanes}) : std::min(r.omega - done, max_lanes);
-        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(paths, max_lanes / chunk));
-        const int64_t per_lane = (paths + K - 1) / K;
-        if (tag_next + (uint64_t)per_lane >= ((uint64_t)1 << 32)) {
-            HIP_TRY(launch_fill_u64(g->pair_cnt.as<uint64_t>(), 0ull, max_lanes * n, s));
-            tag_next = 1;
-        }
+        // samples of this launch: all of them, within the Wilson slots when
+        // checking, and within the queue's capacity in the hashed form
+        int64_t chunk = r.omega - done;
+        if (check) chunk = std::min(chunk, r.slots);
+        if (hashed) chunk = std::max<int64_t>(1, std::min(chunk, (2 * kPairMaxPairs) / paths));
+        const int64_t items = chunk * paths;
         PairParams p;
         std::memset(&p, 0, sizeof p);
         if (check) {
@@ -768,10 +807,8 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
         p.ps = d_ids;
         p.pt = d_ids + n_pairs;
         p.n_pairs = n_pairs;
-        p.cnt = g->pair_cnt.as<uint64_t>();
-        p.n_lanes = chunk * K;
-        p.lanes_per_sample = (int32_t)K;
-        p.tag_base = (uint32_t)tag_next;
+        p.n_items = items;
+        p.next = g->pair_next.as<unsigned long long>();
         p.sample_begin = r.begin + done;
         p.n_total = r.total;
         p.n_blocks = r.B;
@@ -779,12 +816,49 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
         p.stats = g->stats.as<unsigned long long>();
         p.err = g->err.as<DevErr>();
         p.deadline = (uint64_t)(tmo * g->clock_khz * 1000.0);
-        tm.begin("pair_paths", s);
-        HIP_TRY(launch_pair_paths(p, s));
-        tm.end(s);
-        if ((rc = finish(g, s, tm)) != LAP_OK) return rc;
-        for (int i = 0; i < kNumStats; ++i) acc[i] += g->last_stats[i];
-        tag_next += (uint64_t)per_lane;
+        if (hashed) {
+            const int64_t L = std::min(hash_cap, items);
+            if ((rc = ready_lanes(g->pair_tbl, g->pair_tbl_tags, g->pair_tbl_lanes, L, hash_words, s)) != LAP_OK)
+                return rc;
+            if (g->pair_queue.ensure(sizeof(uint64_t) * (size_t)(items + 1)))
+                return fail(LAP_ENOMEM, "cannot allocate pair path queue");
+            p.tbl = g->pair_tbl.as<uint64_t>();
+            p.lane_tag = g->pair_tbl_tags.as<uint32_t>();
+            p.hash_log2 = kPairHashLog2;
+            p.hash_limit = (int32_t)(hash_words * 3 / 4);
+            p.queue_out_len = g->pair_queue.as<unsigned long long>();
+            p.queue_out = p.queue_out_len + 1;
+            HIP_TRY(launch_fill_u64((uint64_t *)p.queue_out_len, 0ull, 1, s));
+            if ((rc = run(p, true, L)) != LAP_OK) return rc;
+            // paths that filled their table run again in the dense form
+            unsigned long long queued = 0;
+            HIP_TRY(hipMemcpy(&queued, p.queue_out_len, sizeof queued, hipMemcpyDeviceToHost));
+            hashed_items += items;
+            queued_total += (int64_t)queued;
+            if (queued > 0) {
+                const int64_t Ld = std::min<int64_t>(dense_cap, (int64_t)queued);
+                if ((rc = ready_lanes(g->pair_cnt, g->pair_cnt_tags, g->pair_cnt_lanes, Ld, n, s)) != LAP_OK)
+                    return rc;
+                HIP_TRY(launch_fill_u64(g->err.as<uint64_t>(), 0ull, 1, s));
+                HIP_TRY(launch_fill_u64(g->stats.as<uint64_t>(), 0ull, kNumStats, s));
+                PairParams d = p;
+                d.tbl = nullptr;
+                d.cnt = g->pair_cnt.as<uint64_t>();
+                d.lane_tag = g->pair_cnt_tags.as<uint32_t>();
+                d.queue_in = p.queue_out;
+                d.queue_in_len = p.queue_out_len;
+                d.queue_out = d.queue_out_len = nullptr;
+                if ((rc = run(d, false, Ld)) != LAP_OK) return rc;
+            }
+            // when many paths outgrow the tables, the dense form takes the rest
+            if (queued_total * 4 > hashed_items) hashed = false;
+        } else {
+            const int64_t L = std::min(dense_cap, items);
+            if ((rc = ready_lanes(g->pair_cnt, g->pair_cnt_tags, g->pair_cnt_lanes, L, n, s)) != LAP_OK) return rc;
+            p.cnt = g->pair_cnt.as<uint64_t>();
+            p.lane_tag = g->pair_cnt_tags.as<uint32_t>();
+            if ((rc = run(p, false, L)) != LAP_OK) return rc;
+        }
         done += chunk;
     }
     for (int i = 0; i < kNumStats; ++i) g->last_stats[i] = acc[i];

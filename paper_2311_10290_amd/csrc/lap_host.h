@@ -87,7 +87,10 @@ struct lap_graph {
     int32_t bfs_root = -1;
     lap::DevBuf bfs_par, span64, span32, span_x, span_s;
     lap::DevBuf loop_cnt, loop_y2, loop_len;   // loop-included paths
-    lap::DevBuf pair_cnt, pair_ids, pair_v, pair_out;   // loop-included paths from node pairs
+    // loop-included paths from node pairs: per-lane counter words and last
+    // tags (dense and hashed forms; lanes set up so far), queue, counters
+    lap::DevBuf pair_cnt, pair_cnt_tags, pair_tbl, pair_tbl_tags, pair_queue, pair_next, pair_ids, pair_v, pair_out;
+    int64_t pair_cnt_lanes = 0, pair_tbl_lanes = 0;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t last_stats[lap::kNumStats] = {0};
@@ -95,7 +98,8 @@ struct lap_graph {
         lap::DevBuf *bufs[] = {&rp, &nbr, &col, &arcs, &state, &epoch, &y1, &y2, &y1s, &len_u, &len_p, &keep_next,
                           &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount,
                           &bfs_par, &span64, &span32, &span_x, &span_s, &loop_cnt, &loop_y2, &loop_len,
-                          &pair_cnt, &pair_ids, &pair_v, &pair_out};
+                          &pair_cnt, &pair_cnt_tags, &pair_tbl, &pair_tbl_tags, &pair_queue, &pair_next,
+                          &pair_ids, &pair_v, &pair_out};
         for (lap::DevBuf *b : bufs) b->release();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);

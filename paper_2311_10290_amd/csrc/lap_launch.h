@@ -49,7 +49,7 @@ hipError_t launch_spantree(const SpanParams &p, hipStream_t s);
 hipError_t launch_span_assemble(const SpanAsmParams &p, hipStream_t s);
 int64_t span_assemble_parts(int64_t n);
 hipError_t launch_loop_included(const LoopParams &p, hipStream_t s);
-hipError_t launch_pair_paths(const PairParams &p, hipStream_t s);
+hipError_t launch_pair_paths(const PairParams &p, bool hashed, hipStream_t s);
 hipError_t launch_pair_assemble(const PairAsmParams &p, hipStream_t s);
 hipError_t launch_serve(const ServeParams &p, int64_t waves, hipStream_t s);
 hipError_t launch_serve_group(const ServeParams &p, int waves, int64_t groups, hipStream_t s);

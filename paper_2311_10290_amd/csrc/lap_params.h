@@ -121,10 +121,18 @@ struct PairParams {
     const uint32_t *slot_epoch;    // [samples], with state
     const int32_t *ps, *pt;        // [n_pairs]
     int64_t n_pairs;
-    uint64_t *cnt;                 // [n_lanes][n] departures of the lane's current path: tag << 32 | count
-    int64_t n_lanes;               // samples of the launch * lanes_per_sample
-    int32_t lanes_per_sample;
-    uint32_t tag_base;             // tag of each lane's first path in this launch (tags are never 0)
+    uint64_t *cnt;                 // dense form: [n_lanes][n] tag << 32 | count
+    uint64_t *tbl;                 // hashed form: [n_lanes][2^hash_log2] node | tag << 32 | count << 48
+    int32_t hash_log2, hash_limit; // table size, and distinct nodes a path may meet in it
+    uint32_t *lane_tag;            // [n_lanes] last tag each lane used in its words
+    int64_t n_lanes;
+    int64_t n_items;               // items slot * 2 n_pairs + q of the launch (when queue_in is null)
+    const unsigned long long *queue_in;      // or the items to run: [*queue_in_len]
+    const unsigned long long *queue_in_len;
+    unsigned long long *queue_out;           // hashed form: items left to the dense form
+    unsigned long long *queue_out_len;
+    unsigned long long *next;      // [n_parts * 16] item counters, zero before the launch
+    int32_t n_parts;
     int64_t sample_begin, n_total;
     int32_t n_blocks;
     unsigned long long *V;         // [B][n_pairs][4]

@@ -61,64 +61,210 @@ hipError_t launch_loop_included(const LoopParams &p, hipStream_t s) {
 // from u, stack entry S_i[u][c]: the draw (i, u, c, qid).  Its departures from
 // u, divided by d_u, estimate (L_v^{-1})_su, and
 //   r(s,t) = (L_v^{-1})_ss + (L_v^{-1})_tt - 2 (L_v^{-1})_st.
-// Lane l of the launch works for sample l / K (K lanes per sample) and runs
-// paths q = l % K, l % K + K, ... of the 2 n_pairs paths (q even: from s_j,
-// odd: from t_j, j = q / 2).  Each lane owns an n-word counter array; a word
-// holds the tag of the path that last wrote it and its departure count, so a
-// new path starts from zero by taking a new tag, with no clearing between
-// paths.  With the Wilson trees of the launch's samples at hand, every
-// departure also checks that the entry it uses was drawn by the sampler
-// (c < k_u; Wilson's stacks do not depend on the start order, so the path
-// from any s uses no entry the sampler did not).
-__global__ __launch_bounds__(64) void pair_paths_kernel(PairParams p) {
-    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane >= p.n_lanes) return;
-    const int64_t n = p.n;
-    const int64_t slot = lane / p.lanes_per_sample;
-    const int64_t i = p.sample_begin + slot;
-    const uint64_t *st = p.state ? p.state + slot * n : nullptr;
-    const uint32_t ep = st ? p.slot_epoch[slot] : 0u;
-    uint64_t *cnt = p.cnt + lane * n;
-    unsigned long long *Vb = p.V + ((i * (int64_t)p.n_blocks) / p.n_total) * p.n_pairs * 4;
-    const uint64_t t0 = wall_clock64();
-    unsigned long long steps = 0;
-    uint32_t tag = p.tag_base;
-    for (int64_t q = lane % p.lanes_per_sample; q < 2 * p.n_pairs; q += p.lanes_per_sample, ++tag) {
-        const int64_t j = q >> 1;
-        const bool from_t = (q & 1) != 0;
-        const int32_t from = from_t ? p.pt[j] : p.ps[j];
-        const int32_t other = from_t ? p.ps[j] : p.pt[j];
-        int32_t u = from;
-        while (u != p.root) {
-            const uint64_t e = cnt[u];
-            const uint32_t c = ((uint32_t)(e >> 32) == tag) ? (uint32_t)e : 0u;
-            if (st ? c >= st_k(st[u], ep) : c == 0xffffffffu) {
-                raise_err(p.err, kErrInconsistent, -21);
-                return;
+// Work item slot * 2 n_pairs + q: path q (q even: from s_j, odd: from t_j,
+// j = q / 2) through the stacks of sample sample_begin + slot.
+//
+// Path lengths spread widely, so a lane does not wait for the other lanes of
+// its wave: whenever its path ends it takes the next item, from one of
+// n_parts counters (workgroup b uses part b mod n_parts), one atomic per wave
+// for all lanes that need an item.
+//
+// A lane keeps the departure counts of its current path in one of two forms:
+//   dense  one 8-byte word per node (tag << 32 | count);
+//   hashed an open-addressing table of 2^hash_log2 words (node | tag << 32 |
+//          count << 48), probed linearly from a multiplicative hash; a path
+//          that meets more than hash_limit distinct nodes, or departs 2^16-1
+//          times from one node, is abandoned before it adds anything and
+//          queued for the dense form.
+// A word belongs to the current path only if it carries the path's tag, so a
+// new path starts from zero by taking the lane's next tag; only when the tags
+// run out does a lane clear its own words.  Each lane's last tag persists in
+// lane_tag between launches.  With the Wilson trees of the launch's samples
+// at hand, every departure also checks that the entry it uses was drawn by the
+// sampler (c < k_u: Wilson's stacks do not depend on the start order, so the
+// path from any s uses no entry the sampler did not).
+constexpr uint32_t kDepFull = 0xffffffffu;
+
+struct DenseDepartures {
+    uint64_t *w;
+    int64_t words;
+    uint32_t tag;
+    static constexpr uint32_t kTagMax = 0xffffffffu;
+    __device__ __forceinline__ void clear() {
+        for (int64_t k = 0; k < words; ++k) w[k] = 0ull;
+    }
+    __device__ __forceinline__ void start(uint32_t t) { tag = t; }
+    __device__ __forceinline__ uint32_t get(int32_t u) const {
+        const uint64_t e = w[u];
+        return ((uint32_t)(e >> 32) == tag) ? (uint32_t)e : 0u;
+    }
+    // count before this departure from u, or kDepFull
+    __device__ __forceinline__ uint32_t bump(int32_t u) {
+        const uint32_t c = get(u);
+        if (c == kDepFull - 1) return kDepFull;
+        w[u] = ((uint64_t)tag << 32) | (uint64_t)(c + 1);
+        return c;
+    }
+};
+
+struct HashDepartures {
+    uint64_t *w;
+    int64_t words;
+    uint32_t mask, shift, tag;
+    int32_t distinct, limit;
+    static constexpr uint32_t kTagMax = 0xffffu;
+    __device__ __forceinline__ void clear() {
+        for (int64_t k = 0; k < words; ++k) w[k] = 0ull;
+    }
+    __device__ __forceinline__ void start(uint32_t t) {
+        tag = t;
+        distinct = 0;
+    }
+    __device__ __forceinline__ uint32_t home(int32_t u) const { return ((uint32_t)u * 2654435761u) >> shift; }
+    __device__ __forceinline__ bool mine(uint64_t e) const { return (uint32_t)((e >> 32) & 0xffffu) == tag; }
+    __device__ __forceinline__ uint32_t get(int32_t u) const {
+        for (uint32_t h = home(u);; h = (h + 1) & mask) {   // ends: at most `limit` < 2^hash_log2 words are the path's
+            const uint64_t e = w[h];
+            if (!mine(e)) return 0u;
+            if ((uint32_t)e == (uint32_t)u) return (uint32_t)(e >> 48);
+        }
+    }
+    __device__ __forceinline__ uint32_t bump(int32_t u) {
+        for (uint32_t h = home(u);; h = (h + 1) & mask) {
+            const uint64_t e = w[h];
+            if (!mine(e)) {
+                if (++distinct > limit) return kDepFull;
+                w[h] = (uint64_t)(uint32_t)u | ((uint64_t)tag << 32) | (1ull << 48);
+                return 0u;
             }
-            cnt[u] = ((uint64_t)tag << 32) | (uint64_t)(c + 1);
-            const uint64_t nb = p.nbr[u];
-            const uint64_t x = philox_w0((uint64_t)i, (uint64_t)u, (uint64_t)c, p.qid, p.k0, p.k1);
-            u = p.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
-            ++steps;
-            if ((steps & 1023) == 0 && (wall_clock64() - t0 > p.deadline || err_set(p.err))) {
-                raise_err(p.err, kErrTimeout, 4);
-                return;
+            if ((uint32_t)e == (uint32_t)u) {
+                const uint32_t c = (uint32_t)(e >> 48);
+                if (c == 0xffffu) return kDepFull;
+                w[h] = (e & 0x0000ffffffffffffull) | ((uint64_t)(c + 1) << 48);
+                return c;
             }
         }
-        // departures from the start and from the other node (the root never departs)
-        const uint64_t eh = cnt[from], eo = cnt[other];
-        const unsigned long long here = (from != p.root && (uint32_t)(eh >> 32) == tag) ? (uint32_t)eh : 0u;
-        const unsigned long long there = (other != p.root && (uint32_t)(eo >> 32) == tag) ? (uint32_t)eo : 0u;
-        unsigned long long *row = Vb + j * 4;
-        if (here) atomicAdd(&row[from_t ? 2 : 0], here);
-        if (there) atomicAdd(&row[from_t ? 3 : 1], there);
     }
+};
+
+template <class Dep>
+__device__ void pair_lane(const PairParams &p, Dep &dep, int64_t lane) {
+    const int64_t n = p.n;
+    const int64_t paths = 2 * p.n_pairs;
+    const int part = (int)(blockIdx.x % (unsigned)p.n_parts);
+    const int64_t n_items = p.queue_in ? (int64_t)*p.queue_in_len : p.n_items;
+    const int64_t lo = n_items * part / p.n_parts, hi = n_items * (part + 1) / p.n_parts;
+    unsigned long long *next = p.next + 16 * part;   // one 128-byte line per part
+    const uint64_t t0 = wall_clock64();
+    const int wl = (int)(threadIdx.x & 63);
+    unsigned long long steps = 0;
+    uint32_t tag = p.lane_tag[lane];
+    // current path
+    int64_t item = -1, j = 0, i = 0;
+    int32_t u = p.root, from = 0, other = 0;
+    bool from_t = false;
+    const uint64_t *st = nullptr;
+    uint32_t ep = 0;
+    for (;;) {
+        if (u == p.root && item >= 0) {
+            // the path reached v: add its departures from s_j and t_j (the root never departs)
+            const unsigned long long here = (from != p.root) ? dep.get(from) : 0u;
+            const unsigned long long there = (other != p.root) ? dep.get(other) : 0u;
+            unsigned long long *row = p.V + (((i * (int64_t)p.n_blocks) / p.n_total) * p.n_pairs + j) * 4;
+            if (here) atomicAdd(&row[from_t ? 2 : 0], here);
+            if (there) atomicAdd(&row[from_t ? 3 : 1], there);
+            item = -1;
+        }
+        const bool need = (u == p.root);
+        const unsigned long long want = __ballot(need);
+        if (want) {
+            const int leader = __ffsll((long long)want) - 1;
+            unsigned long long base = 0;
+            if (wl == leader) base = atomicAdd(next, (unsigned long long)__popcll(want));
+            base = __shfl(base, leader);
+            if (need) {
+                const int64_t e = lo + (int64_t)base + __popcll(want & ((1ull << wl) - 1ull));
+                if (e >= hi) break;
+                item = p.queue_in ? (int64_t)p.queue_in[e] : e;
+                const int64_t slot = item / paths, q = item % paths;
+                i = p.sample_begin + slot;
+                st = p.state ? p.state + slot * n : nullptr;
+                ep = st ? p.slot_epoch[slot] : 0u;
+                j = q >> 1;
+                from_t = (q & 1) != 0;
+                from = from_t ? p.pt[j] : p.ps[j];
+                other = from_t ? p.ps[j] : p.pt[j];
+                if (tag == Dep::kTagMax) {   // tags used up: clear this lane's words
+                    dep.clear();
+                    tag = 0;
+                }
+                dep.start(++tag);
+                u = from;
+                continue;   // a path from the root ends at once
+            }
+        }
+        // one departure from u
+        const uint64_t nb = p.nbr[u];   // independent of the count: in flight with the probe
+        const uint64_t sw = st ? st[u] : 0ull;
+        const uint32_t c = dep.bump(u);
+        if (c == kDepFull) {
+            if (!p.queue_out) {   // dense form: 2^32-1 departures from one node
+                raise_err(p.err, kErrDrawOverflow, -22);
+                break;
+            }
+            const unsigned long long at = atomicAdd(p.queue_out_len, 1ull);
+            p.queue_out[at] = (unsigned long long)item;   // capacity: every item of the launch
+            item = -1;
+            u = p.root;
+            continue;
+        }
+        if (st && c >= st_k(sw, ep)) {
+            raise_err(p.err, kErrInconsistent, -21);
+            break;
+        }
+        const uint64_t x = philox_w0((uint64_t)i, (uint64_t)u, (uint64_t)c, p.qid, p.k0, p.k1);
+        u = p.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
+        ++steps;
+        if ((steps & 1023) == 0 && (wall_clock64() - t0 > p.deadline || err_set(p.err))) {
+            raise_err(p.err, kErrTimeout, 4);
+            break;
+        }
+    }
+    p.lane_tag[lane] = tag;
     atomicAdd(&p.stats[kStatAbsorbed], steps);
 }
 
-hipError_t launch_pair_paths(const PairParams &p, hipStream_t s) {
-    hipLaunchKernelGGL(pair_paths_kernel, dim3((unsigned)((p.n_lanes + 63) / 64)), dim3(64), 0, s, p);
+__global__ __launch_bounds__(64) void pair_paths_hash_kernel(PairParams p) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= p.n_lanes) return;
+    HashDepartures dep;
+    dep.words = (int64_t)1 << p.hash_log2;
+    dep.w = p.tbl + lane * dep.words;
+    dep.mask = (1u << p.hash_log2) - 1u;
+    dep.shift = 32u - (uint32_t)p.hash_log2;
+    dep.limit = p.hash_limit;
+    dep.tag = 0;
+    dep.distinct = 0;
+    pair_lane(p, dep, lane);
+}
+
+__global__ __launch_bounds__(64) void pair_paths_dense_kernel(PairParams p) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lane >= p.n_lanes) return;
+    DenseDepartures dep;
+    dep.words = p.n;
+    dep.w = p.cnt + lane * p.n;
+    dep.tag = 0;
+    pair_lane(p, dep, lane);
+}
+
+hipError_t launch_pair_paths(const PairParams &p, bool hashed, hipStream_t s) {
+    if (p.n_lanes <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((p.n_lanes + 63) / 64);
+    if (hashed)
+        hipLaunchKernelGGL(pair_paths_hash_kernel, dim3(blocks), dim3(64), 0, s, p);
+    else
+        hipLaunchKernelGGL(pair_paths_dense_kernel, dim3(blocks), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 

@@ -76,6 +76,9 @@ def test_pair_paths_mid_workload_bit_exact():
         log(f"pairs ba100k check {check}")
         got = hg.pair_paths(s, t, 256, 1, root, B=8, check=check)
         _same(og, got, s, t, 256, 1, 8, root)
+    log("pairs ba100k lanes 300")
+    got = hg.pair_paths(s, t, 256, 1, root, B=8, check=0, lanes=300)
+    _same(og, got, s, t, 256, 1, 8, root)
 
 
 def test_pair_paths_many_pairs_few_samples_and_resume():
@@ -94,6 +97,37 @@ def test_pair_paths_many_pairs_few_samples_and_resume():
     b = hg.pair_paths(s, t, 25, 2, root, B=4, sample_begin=15, n_total=40, mode=3, group=2)
     assert np.array_equal(a["V"] + b["V"], full["V"])
     _same(og, full, s, t, 40, 2, 4, root)
+    # few lanes: many launches, each lane's counters reused under new tags
+    for lanes, check in ((7, 0), (64, 0), (5, 1), (100, 1)):
+        log(f"pairs ba5k lanes {lanes} check {check}")
+        got = hg.pair_paths(s, t, 40, 2, root, B=4, check=check, lanes=lanes, pool=6)
+        assert np.array_equal(got["V"], full["V"])
+
+
+def test_pair_paths_tables_that_fill_up_bit_exact():
+    """Graphs with more nodes than a lane's table has words take the hashed
+    form.  On these Erdos-Renyi graphs 6%, 24% and 31% of the paths meet
+    more distinct nodes than a table allows and run again in the dense form
+    (past a quarter, the rest of the call stays dense).  With few lanes the
+    call takes many launches."""
+    import graphgen as gg
+    for n, deg, seed, lanes in ((20_000, 8, 0, 97), (30_000, 8, 2, 0), (40_000, 10, 4, 1000)):
+        src, dst = gg.erdos_renyi(n, deg / n, seed)
+        og, hg = both(n, src, dst, keep_lcc=True)
+        root = csr.landmark(og)
+        s, t = _pairs(og.n, root, 24, seed + 8)
+        omega = 16
+        # precondition: some of these paths outgrow a table (more than 12288 distinct nodes)
+        big = 0
+        for i in range(omega):
+            for a in np.concatenate([s, t]):
+                tr = native.loop_included_path(og.n, root, int(a), g=og, sample=i, seed=3, trace_cap=1 << 24)
+                big += len(np.unique(tr[:-1])) > 12288
+        assert big > 0
+        for check in (0, 1):
+            log(f"pairs er{n} lanes {lanes} check {check}")
+            got = hg.pair_paths(s, t, omega, 3, root, B=4, check=check, lanes=lanes)
+            _same(og, got, s, t, omega, 3, 4, root)
 
 
 def test_pair_paths_argument_errors():
@@ -106,5 +140,7 @@ def test_pair_paths_argument_errors():
         hg.pair_paths([0, 300], [1, 2], 10, 1)
     with pytest.raises(LapError):
         hg.pair_paths([0], [-1], 10, 1)
+    with pytest.raises(LapError):
+        hg.pair_paths([0], [1], 10, 1, lanes=-1)
     with pytest.raises(ValueError):
         hg.pair_paths([0, 1], [1], 10, 1)
