@@ -11,8 +11,9 @@
 //           with the wave-cooperative sampler;
 //   kind 1  64 uniform-start absorbed walks of one job, one per lane;
 //   kind 2  64 stationary-start absorbed walks of one job.
-// Items are ordered largest graphs first (longest chunks first), walk tiles
-// last, so short items fill the tail.
+// Items come job by job, largest graphs first (Wilson chunks, then walk
+// tiles), so the waves in flight share a few graphs and short items fill the
+// tail.
 #include "lap_device.h"
 #include "lap_launch.h"
 #include "walks.h"

@@ -159,8 +159,10 @@ bool same_shape(const lap_batch_tuning &a, const lap_batch_tuning &c) {
     return a.pool == c.pool && a.chunk_nodes == c.chunk_nodes && a.timeout_s == c.timeout_s;
 }
 
-// Wilson chunks of about chunk_nodes node-samples, largest graphs first, then
-// 64-walk tiles of both kinds.
+// Job by job, largest graphs first: the job's Wilson chunks of about
+// chunk_nodes node-samples, then its 64-walk tiles of both kinds.  Keeping a
+// job's items together keeps the waves in flight on a few graphs at a time,
+// whose rows and columns then stay in the caches.
 int build_items(lap_batch *b, const lap_batch_tuning &t) {
     if (b->have_items && b->items_for.chunk_nodes == t.chunk_nodes) return LAP_OK;
     std::vector<BatchItem> items;
@@ -171,12 +173,9 @@ int build_items(lap_batch *b, const lap_batch_tuning &t) {
         const BatchJobDev &d = b->jobs[j];
         const int64_t per = std::max<int64_t>(1, (int64_t)t.chunk_nodes / std::max<int64_t>(d.n, 1));
         for (int64_t s = 0; s < d.omega; s += per) items.push_back({j, 0, s, std::min(per, d.omega - s)});
-    }
-    for (int kind = 1; kind <= 2; ++kind)
-        for (int32_t j : order) {
-            const BatchJobDev &d = b->jobs[j];
+        for (int kind = 1; kind <= 2; ++kind)
             for (int64_t s = 0; s < d.omega; s += 64) items.push_back({j, kind, s, std::min<int64_t>(64, d.omega - s)});
-        }
+    }
     if (b->items_d.ensure(sizeof(BatchItem) * items.size()))
         return fail(LAP_ENOMEM, "cannot allocate the work-item table");
     HIP_TRY(hipMemcpy(b->items_d.ptr, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
