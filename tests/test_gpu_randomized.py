@@ -57,3 +57,54 @@ def test_random_graph_counts_bit_exact(case):
     assert np.array_equal(got["next"], w["next"]) and np.array_equal(got["draws"], w["draws"])
     assert np.array_equal(got["Y2"], a["Y2"]) and np.array_equal(got["len_uniform"], a["len"])
     assert np.array_equal(got["len_pi"], p["len"])
+
+
+def _pair_graph(rng, i):
+    # every third case is large enough for the hashed form (more than 16384 nodes)
+    if i % 3 == 2:
+        if i % 2:
+            n = int(rng.integers(17_000, 40_000))
+            s, d = gg.barabasi_albert(n, int(rng.integers(2, 6)), int(rng.integers(1 << 30)))
+            return n, s, d, False
+        scale = 15
+        s, d = gg.rmat(scale, 8, seed=int(rng.integers(1 << 30)))
+        return 1 << scale, s, d, True
+    return _graph(rng, i)
+
+
+@pytest.mark.parametrize("case", range(18))
+def test_random_pair_paths_bit_exact(case):
+    """Node-pair paths (lap_pair_paths) on random graphs, roots, pairs, seeds,
+    ids, block counts, sample ranges, lane caps, sampler forms and both check
+    settings: the per-block sums equal the oracle's."""
+    rng = np.random.default_rng(5000 + case)
+    n, s, d, lcc = _pair_graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=lcc)
+    large = og.n > 16384
+    # on the large graphs a low-degree root makes paths of ~2m/d_v steps: keep the landmark there
+    root = int(rng.integers(0, og.n)) if (case % 4 and not large) else csr.landmark(og)
+    P = int(rng.integers(1, 40))
+    ps = rng.integers(0, og.n, P).astype(np.int32)
+    pt = rng.integers(0, og.n, P).astype(np.int32)
+    if P > 2:
+        ps[0] = root
+        pt[1] = ps[1]
+    omega = int(rng.integers(1, 40))
+    begin = int(rng.integers(0, 5))
+    total = begin + omega + int(rng.integers(0, 5))
+    B = int(rng.integers(1, min(total, 6) + 1))
+    seed = int(rng.integers(1 << 62))
+    stream = int(rng.integers(0, 4))
+    qid = int(rng.integers(0, 1 << 40))
+    mode, group = [(1, 0), (2, 0), (3, 2), (3, 4), (3, 8)][case % 5]
+    check = case % 2
+    lanes = [0, 1, 7, 64, 1000][int(rng.integers(0, 5))]
+    if large:
+        lanes = max(lanes, 64)
+    log(f"random pair case {case}: n={og.n} root={root} pairs={P} omega={omega} begin={begin} "
+        f"mode={mode}/{group} check={check} lanes={lanes}")
+    got = hg.pair_paths(ps, pt, omega, seed, root, B=B, check=check, lanes=lanes, sample_begin=begin,
+                        n_total=total, mode=mode, group=group, stream_id=stream, qid=qid)
+    exp = native.pair_paths(og, root, omega, seed, ps, pt, stream=stream, qid=qid, sample_begin=begin,
+                            omega_total=total, B=B)
+    assert np.array_equal(got["V"], exp)
