@@ -345,11 +345,16 @@ int finish(lap_graph *g, hipStream_t s, Timer &tm) {
         g->state_dirty = true;
         switch (e.code) {
             case kErrDrawOverflow:
+                if (e.detail == -22)
+                    return fail(LAP_ERANGE, "a node-pair path departed 2^32-1 times from one node");
                 return fail(LAP_ERANGE, "more than 2^21-1 draws at node " + std::to_string(e.detail) +
                                             " in one sample");
             case kErrTimeout:
                 return fail(LAP_ERANGE, "kernel time limit exceeded");
             default:
+                if (e.detail == -20 || e.detail == -21)
+                    return fail(LAP_EDEVICE, "a loop-included path needed a stack entry its Wilson sample did "
+                                             "not draw");
                 return fail(LAP_EDEVICE, "walker state inconsistent (tree count " +
                                              std::to_string(e.detail) + ")");
         }
