@@ -315,11 +315,16 @@ def bench_kc_families(lap, gg, n):
         s, d = gg.hyperbolic(n, 10.0, gamma, 300 + int(round(gamma * 10)))
         jobs.append(dict(n=n, src=s, dst=d, keep_lcc=True, root=-1, omega=256, seed=1))
         labels.append(f"hyperbolic gamma={gamma}")
+    log(f"kc families: {len(jobs)} graphs generated in {time.perf_counter() - t0:.1f} s "
+        f"({sum(len(j['src']) for j in jobs) / 1e6:.0f} M edges)")
     b = lap.Batch(jobs)
+    del jobs
     gen_s = time.perf_counter() - t0
+    log(f"kc families: batch built in {gen_s:.1f} s")
     tuning = lap.Batch.tuning()
     b.run(tuning)
     torch.cuda.synchronize()
+    log("kc families: warm-up run done")
     t = time.perf_counter()
     b.run(tuning)
     torch.cuda.synchronize()

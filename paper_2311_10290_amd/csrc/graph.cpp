@@ -1,49 +1,45 @@
 // Host-side graph ingest: raw undirected edge list -> simple connected CSR
 // (the input the paper's methods assume, Sec. 2).  Steps:
-//   1. both orientations of every non-loop pair become 64-bit keys row*n+col;
-//   2. LSD radix sort of the keys, adjacent duplicates dropped;
-//   3. connected components by union-find over the kept pairs;
-//   4. not connected: keep the largest component (ties: the one holding the
-//      smallest id) and renumber its nodes by ascending original id, or fail;
-//   5. row offsets by counting; neighbours come out sorted ascending.
+//   1. degrees of both orientations of every non-loop pair, row offsets;
+//   2. each pair scattered into both rows;
+//   3. every row sorted and its duplicates dropped (rows split over threads);
+//   4. connected components by breadth-first search from the smallest
+//      unlabelled id;
+//   5. not connected: keep the largest component (ties: the one holding the
+//      smallest id) and renumber its nodes by ascending original id, or fail.
+// Neighbours come out sorted ascending.
 #include <stdint.h>
 
 #include <algorithm>
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "lap_host.h"
 
 namespace lap {
 
-static void radix_sort_u64(std::vector<uint64_t> &a, int bits) {
-    const int kDigit = 11;
-    const size_t n = a.size();
-    std::vector<uint64_t> tmp(n);
-    std::vector<size_t> cnt(1u << kDigit);
-    for (int shift = 0; shift < bits; shift += kDigit) {
-        std::fill(cnt.begin(), cnt.end(), 0);
-        const uint64_t mask = (1ull << kDigit) - 1;
-        for (size_t i = 0; i < n; ++i) ++cnt[(a[i] >> shift) & mask];
-        size_t sum = 0;
-        for (auto &c : cnt) {
-            const size_t t = c;
-            c = sum;
-            sum += t;
-        }
-        for (size_t i = 0; i < n; ++i) tmp[cnt[(a[i] >> shift) & mask]++] = a[i];
-        a.swap(tmp);
+// Runs f(lo, hi) over [0, rows) split into contiguous ranges of about equal
+// weight (weights given by the row offsets rp), one range per thread.
+template <class F>
+static void for_row_ranges(int64_t rows, const std::vector<int64_t> &rp, F f) {
+    const int64_t total = rp[rows];
+    int64_t T = (int64_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (total < ((int64_t)1 << 20)) T = 1;
+    std::vector<std::thread> th;
+    int64_t lo = 0;
+    for (int64_t t = 0; t < T && lo < rows; ++t) {
+        const int64_t goal = total * (t + 1) / T;
+        int64_t hi = (t == T - 1) ? rows : (int64_t)(std::upper_bound(rp.begin(), rp.begin() + rows + 1, goal) - rp.begin()) - 1;
+        hi = std::max(hi, lo + 1);
+        hi = std::min(hi, rows);
+        if (t == T - 1) hi = rows;
+        th.emplace_back(f, lo, hi);
+        lo = hi;
     }
-}
-
-static int32_t uf_find(std::vector<int32_t> &par, int32_t x) {
-    while (par[x] != x) {
-        par[x] = par[par[x]];
-        x = par[x];
-    }
-    return x;
+    for (auto &x : th) x.join();
 }
 
 int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst, bool keep_lcc,
@@ -56,80 +52,139 @@ int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t
         err = "bad edge arrays";
         return LAP_EINVAL;
     }
-    std::vector<uint64_t> keys;
+    // Edges are split into T contiguous chunks, one per thread.  Each thread
+    // counts its chunk's row entries, then writes them into its own slots of
+    // every row (slot ranges come from the per-thread counts), so the random
+    // writes of the scatter run on all threads.
+    const int64_t hw = (int64_t)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int64_t T = std::max<int64_t>(1, std::min<int64_t>(hw, ((int64_t)1 << 28) / n));   // T * n counters
+    if (n_edges < ((int64_t)1 << 20)) T = 1;
+    std::vector<int64_t> rp;
+    std::vector<uint32_t> cnt;   // [T][n] entries of thread t's chunk in row u, then its next slot offset
+    std::vector<int32_t> adj;
+    std::vector<int64_t> bad((size_t)T, -1);
+    auto run = [&](auto f) {
+        std::vector<std::thread> th;
+        for (int64_t t = 0; t < T; ++t) th.emplace_back(f, t, n_edges * t / T, n_edges * (t + 1) / T);
+        for (auto &x : th) x.join();
+    };
     try {
-        keys.reserve((size_t)n_edges * 2);
+        rp.assign((size_t)n + 1, 0);
+        cnt.assign((size_t)(T * n), 0u);
     } catch (...) {
         err = "host allocation failed";
         return LAP_ENOMEM;
     }
-    const uint64_t N = (uint64_t)n;
-    for (int64_t e = 0; e < n_edges; ++e) {
-        const int64_t a = src[e], b = dst[e];
-        if (a < 0 || a >= n || b < 0 || b >= n) {
-            err = "edge " + std::to_string(e) + " has a node id outside [0, n)";
+    run([&](int64_t t, int64_t lo, int64_t hi) {
+        uint32_t *c = cnt.data() + t * n;
+        for (int64_t e = lo; e < hi; ++e) {
+            const int64_t a = src[e], b = dst[e];
+            if (a < 0 || a >= n || b < 0 || b >= n) {
+                bad[t] = e;
+                return;
+            }
+            if (a == b) continue;
+            ++c[a];
+            ++c[b];
+        }
+    });
+    for (int64_t t = 0; t < T; ++t)
+        if (bad[t] >= 0) {
+            err = "edge " + std::to_string(bad[t]) + " has a node id outside [0, n)";
             return LAP_EINVAL;
         }
-        if (a == b) continue;
-        keys.push_back((uint64_t)a * N + (uint64_t)b);
-        keys.push_back((uint64_t)b * N + (uint64_t)a);
-    }
-    int bits = 1;
-    const uint64_t maxkey = N * N;
-    while (bits < 64 && (1ull << bits) < maxkey) ++bits;
-    radix_sort_u64(keys, bits);
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-
-    // connected components
-    std::vector<int32_t> par((size_t)n);
-    std::iota(par.begin(), par.end(), 0);
-    for (uint64_t k : keys) {
-        const int32_t a = (int32_t)(k / N), b = (int32_t)(k % N);
-        if (a < b) {
-            const int32_t ra = uf_find(par, a), rb = uf_find(par, b);
-            if (ra != rb) par[std::max(ra, rb)] = std::min(ra, rb);   // root = smallest id
-        }
-    }
-    std::vector<int64_t> size((size_t)n, 0);
-    int64_t ncomp = 0;
+    // row offsets, and each thread's first slot in every row (relative to the row)
     for (int64_t u = 0; u < n; ++u) {
-        const int32_t r = uf_find(par, (int32_t)u);
-        if (size[r]++ == 0) ++ncomp;
-    }
-    int32_t keep_root = 0;
-    if (ncomp > 1) {
-        if (!keep_lcc) {
-            err = "graph has " + std::to_string(ncomp) + " connected components";
-            return LAP_ENOTCONN;
+        uint64_t at = 0;
+        for (int64_t t = 0; t < T; ++t) {
+            const uint32_t c = cnt[(size_t)(t * n + u)];
+            cnt[(size_t)(t * n + u)] = (uint32_t)at;
+            at += c;
         }
-        // roots are the smallest ids of their components; scanning ids upward
-        // and taking the first strict maximum breaks ties by smallest id
-        int64_t best = -1;
-        for (int64_t u = 0; u < n; ++u)
-            if (par[u] == (int32_t)u && size[u] > best) {
-                best = size[u];
-                keep_root = (int32_t)u;
+        if (at > 0xffffffffull) {
+            err = "node " + std::to_string(u) + " has 2^32 or more edge entries";
+            return LAP_EINVAL;
+        }
+        rp[u + 1] = rp[u] + (int64_t)at;
+    }
+    try {
+        adj.resize((size_t)rp[n]);
+    } catch (...) {
+        err = "host allocation failed";
+        return LAP_ENOMEM;
+    }
+    run([&](int64_t t, int64_t lo, int64_t hi) {
+        uint32_t *c = cnt.data() + t * n;
+        for (int64_t e = lo; e < hi; ++e) {
+            const int32_t a = src[e], b = dst[e];
+            if (a == b) continue;
+            adj[(size_t)(rp[a] + c[a]++)] = b;
+            adj[(size_t)(rp[b] + c[b]++)] = a;
+        }
+    });
+    std::vector<uint32_t>().swap(cnt);
+    // sort every row and drop duplicates; deg[u] = distinct neighbours
+    std::vector<int64_t> deg((size_t)n, 0);
+    for_row_ranges(n, rp, [&](int64_t lo, int64_t hi) {
+        for (int64_t u = lo; u < hi; ++u) {
+            int32_t *b = adj.data() + rp[u], *e = adj.data() + rp[u + 1];
+            std::sort(b, e);
+            deg[u] = std::unique(b, e) - b;
+        }
+    });
+
+    // connected components: breadth-first search from the smallest unlabelled id
+    std::vector<int32_t> comp((size_t)n, -1), queue;
+    queue.reserve((size_t)n);
+    int64_t ncomp = 0, best = -1;
+    int32_t keep = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        if (comp[s] >= 0) continue;
+        const int32_t c = (int32_t)ncomp++;
+        queue.clear();
+        queue.push_back((int32_t)s);
+        comp[s] = c;
+        for (size_t h = 0; h < queue.size(); ++h) {
+            const int32_t a = queue[h];
+            for (int64_t j = rp[a]; j < rp[a] + deg[a]; ++j) {
+                const int32_t b = adj[(size_t)j];
+                if (comp[b] < 0) {
+                    comp[b] = c;
+                    queue.push_back(b);
+                }
             }
+        }
+        // components are met in order of their smallest id: the first strict
+        // maximum breaks ties by smallest id
+        if ((int64_t)queue.size() > best) {
+            best = (int64_t)queue.size();
+            keep = c;
+        }
+    }
+    if (ncomp > 1 && !keep_lcc) {
+        err = "graph has " + std::to_string(ncomp) + " connected components";
+        return LAP_ENOTCONN;
     }
     std::vector<int32_t> newid((size_t)n, -1);
     out.old_ids.clear();
     for (int64_t u = 0; u < n; ++u)
-        if (ncomp == 1 || uf_find(par, (int32_t)u) == keep_root) {
+        if (comp[u] == keep) {
             newid[u] = (int32_t)out.old_ids.size();
             out.old_ids.push_back((int32_t)u);
         }
     const int64_t n2 = (int64_t)out.old_ids.size();
     out.n = n2;
     out.rp.assign((size_t)n2 + 1, 0);
-    out.col.clear();
-    out.col.reserve(keys.size());
-    for (uint64_t k : keys) {
-        const int32_t a = newid[k / N], b = newid[k % N];
-        if (a < 0 || b < 0) continue;
-        ++out.rp[(size_t)a + 1];
-        out.col.push_back(b);
-    }
-    for (int64_t u = 0; u < n2; ++u) out.rp[u + 1] += out.rp[u];
+    for (int64_t v = 0; v < n2; ++v) out.rp[v + 1] = out.rp[v] + deg[out.old_ids[v]];
+    out.col.resize((size_t)out.rp[n2]);
+    // renumbering keeps the ascending order inside every row
+    for_row_ranges(n2, out.rp, [&](int64_t lo, int64_t hi) {
+        for (int64_t v = lo; v < hi; ++v) {
+            const int64_t u = out.old_ids[v];
+            int32_t *o = out.col.data() + out.rp[v];
+            for (int64_t j = rp[u]; j < rp[u] + deg[u]; ++j) *o++ = newid[adj[(size_t)j]];
+        }
+    });
     return LAP_OK;
 }
 

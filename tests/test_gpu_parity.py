@@ -35,6 +35,17 @@ def test_csr_matches_oracle():
     cases = [("er256",) + er256_edges(), ("ba2000",) + ba_edges(2000, 3)]
     s, d = gg.rmat(12, 8, seed=4)
     cases.append(("rmat12", 4096, s, d))
+    # above 2^20 edges the host builder splits the edges over threads: a
+    # multigraph with self-loops and duplicates, and a disconnected one
+    rng = np.random.default_rng(11)
+    s = rng.integers(0, 150_000, 1_500_000).astype(np.int32)
+    d = rng.integers(0, 150_000, 1_500_000).astype(np.int32)
+    d[:1000] = s[:1000]
+    s, d = np.concatenate([s, s[:5000]]), np.concatenate([d, d[:5000]])
+    cases.append(("multigraph1.5M", 150_000, s, d))
+    s = rng.integers(0, 400_000, 1_200_000).astype(np.int32)
+    d = rng.integers(0, 400_000, 1_200_000).astype(np.int32)
+    cases.append(("sparse1.2M", 400_000, s, d))
     for name, n, s, d in cases + small_cases():
         log(f"csr {name}")
         og, hg = both(n, s, d, keep_lcc=True)
