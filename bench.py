@@ -106,10 +106,27 @@ def cpu_baseline(og, root, omega_full, seed, budget_s=15.0):
         dt = time.perf_counter() - t
         if n_s < omega_full or dt >= 0.6 * budget_s:
             break
+    # one thread on a smaller sample: the per-core rate
+    n1 = max(8, n_s // (2 * threads))
+    t1 = time.perf_counter()
+    w = native.wilson(og, root, omega_full, seed, n_samples=n1, threads=1)
+    a1 = native.absorbed(og, root, n1, seed, 1, omega_total=omega_full, threads=1)
+    a2 = native.absorbed(og, root, n1, seed, 2, omega_total=omega_full, want_y2=False, threads=1)
+    steps1 = int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": steps / dt, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_s} of {omega_full} samples (Wilson + both absorbed-walk kinds), "
                       f"{reps} pass(es), {dt:.1f} s",
-            "trees_per_s": reps * n_s / dt}
+            "trees_per_s": reps * n_s / dt,
+            "single_thread": {"value": steps1 / dt1, "unit": "walk steps/s",
+                              "sample": f"first {n1} samples, {dt1:.1f} s"},
+            "host_cpu": model, "host_cpus": os.cpu_count()}
 
 
 def bench_batch(lap, gg, n_jobs):
