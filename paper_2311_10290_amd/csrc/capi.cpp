@@ -513,9 +513,9 @@ int span_run(lap_graph *g, const lap_sample_args *a, const Resolved &r, hipStrea
         g->bfs_root = r.root;
     }
     // trees per round: the sampling slots, within 48 GiB of tree scratch
-    const int64_t per_tree = (8 + 4 * kSpanInt32PerNode) * std::max<int64_t>(n, 1);
+    const int64_t per_tree = (8 * kSpanInt64PerNode + 4 * kSpanInt32PerNode) * std::max<int64_t>(n, 1);
     const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(r.slots, ((int64_t)48 << 30) / per_tree));
-    if (g->span64.ensure(sizeof(int64_t) * (size_t)slots * n) ||
+    if (g->span64.ensure(sizeof(int64_t) * (size_t)kSpanInt64PerNode * slots * n) ||
         g->span32.ensure(sizeof(int32_t) * (size_t)kSpanInt32PerNode * slots * n) ||
         g->span_x.ensure(sizeof(uint64_t) * 2 * (size_t)r.B * n) ||
         g->span_s.ensure(sizeof(int64_t) * 2 * (size_t)r.omega))

@@ -73,7 +73,8 @@ struct ServeParams {
 };
 
 // SpanTree pass over the trees left in the Wilson state slots (spantree.hip)
-constexpr int64_t kSpanInt32PerNode = 7;   // scratch per node per tree: 7 int32 + 1 int64
+constexpr int64_t kSpanInt64PerNode = 3;   // scratch per node per tree: 3 int64 + 3 int32
+constexpr int64_t kSpanInt32PerNode = 3;
 
 struct SpanParams {
     int64_t n;
@@ -84,8 +85,8 @@ struct SpanParams {
     int64_t sample_begin, n_total;
     int32_t n_blocks;
     const int32_t *bfs_par;        // [n] BFS parents from the root (-1 at the root)
-    int64_t *scratch64;            // [n_trees][n]
-    int32_t *scratch32;            // [n_trees][7][n]
+    int64_t *scratch64;            // [n_trees][3][n]
+    int32_t *scratch32;            // [n_trees][3][n]
     unsigned long long *X1, *X2;   // [B][n] unit-flow and path-support sums, or null
     long long *s1, *s2;            // [n_trees] Kemeny terms of this launch's samples, or null
     DevErr *err;

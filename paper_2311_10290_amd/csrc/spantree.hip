@@ -8,11 +8,18 @@
 //   1. child counts;
 //   2. subtree sizes sz and degree sums psd, bottom-up: every leaf climbs
 //      towards v, and at each parent the last child to arrive carries the
-//      climb on (so every node is finished exactly once);
+//      climb on (so every node is finished exactly once).  A child adds its
+//      size and takes one off the parent's child count in one atomic on a
+//      packed (count, size) word, so the last child reads the parent's final
+//      size from that atomic's return value;
 //   3. sibling offsets: each child reserves a range of its parent's
 //      subtree (any order of siblings gives a valid pre-order);
-//   4. pre-order numbers by pointer jumping: pre[u] = sum over u's tree path
-//      (without v) of 1 + offset, so u's subtree is [pre[u], pre[u] + sz[u]);
+//   4. pre-order numbers by pointer jumping on packed (sum, pointer) words,
+//      in place: pre[u] = sum over u's tree path (without v) of 1 + offset,
+//      so u's subtree is [pre[u], pre[u] + sz[u]).  A word is read and
+//      written whole, so a node reads either the old or the new (sum,
+//      pointer) pair of the node it jumps over, and either keeps the sum
+//      equal to the weights from u up to (not including) the pointer;
 //   5. the BFS-path pass: for every u, each edge (e1, e2) of u's BFS path
 //      that is a tree edge on u's tree path adds its flow in the direction
 //      e1 -> e2: +1 / -1 to x1(u), +/- the path support (sz for unit weights,
@@ -29,23 +36,25 @@ namespace lap {
 
 constexpr int kSpanThreads = 256;
 constexpr int kSpanWave = 64;
+constexpr int kJumpBatch = 4;   // nodes whose jumps one thread has in flight
 
 struct SpanScratch {
-    int64_t *psd;
-    int32_t *cnt, *acc, *sz, *s0, *s1, *u0, *u1;
+    int64_t *psd;    // degree sums of subtrees
+    uint64_t *cs;    // child count << 32 | subtree size
+    uint64_t *su;    // pre-order partial sum << 32 | jump pointer
+    int32_t *acc, *off, *leaf;
 };
 
 __device__ __forceinline__ SpanScratch span_scratch(const SpanParams &p, int64_t slot) {
     SpanScratch s;
-    s.psd = p.scratch64 + slot * p.n;
+    int64_t *a = p.scratch64 + slot * kSpanInt64PerNode * p.n;
+    s.psd = a;
+    s.cs = (uint64_t *)(a + p.n);
+    s.su = (uint64_t *)(a + 2 * p.n);
     int32_t *b = p.scratch32 + slot * kSpanInt32PerNode * p.n;
-    s.cnt = b;
-    s.acc = b + p.n;
-    s.sz = b + 2 * p.n;
-    s.s0 = b + 3 * p.n;
-    s.s1 = b + 4 * p.n;
-    s.u0 = b + 5 * p.n;
-    s.u1 = b + 6 * p.n;
+    s.acc = b;
+    s.off = b + p.n;
+    s.leaf = b + 2 * p.n;
     return s;
 }
 
@@ -53,19 +62,28 @@ __device__ __forceinline__ int64_t span_block(int64_t sample, int32_t B, int64_t
     return (sample * (int64_t)B) / n_total;
 }
 
+__device__ __forceinline__ int32_t cs_size(uint64_t w) { return (int32_t)(uint32_t)w; }
+__device__ __forceinline__ int32_t su_sum(uint64_t w) { return (int32_t)(uint32_t)(w >> 32); }
+__device__ __forceinline__ int32_t su_ptr(uint64_t w) { return (int32_t)(uint32_t)w; }
+__device__ __forceinline__ uint64_t su_pack(int32_t sum, int32_t ptr) {
+    return ((uint64_t)(uint32_t)sum << 32) | (uint64_t)(uint32_t)ptr;
+}
+
 // A tree is processed by one workgroup only, so every exchange below is
 // between threads of one workgroup (one CU): workgroup-scope atomics and
 // fences suffice and keep the L2 out of it.
-__device__ __forceinline__ int64_t ld_acq64(const int64_t *p) {
+template <class T>
+__device__ __forceinline__ T ld_wg(const T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ int32_t ld_acq32(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+template <class T>
+__device__ __forceinline__ void st_wg(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void add32(int32_t *p, int32_t v) {
+__device__ __forceinline__ void add_wg(int64_t *p, int64_t v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void add64(int64_t *p, int64_t v) {
+__device__ __forceinline__ void add_wg(uint64_t *p, uint64_t v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -84,13 +102,13 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
     SpanScratch s = span_scratch(p, slot);
     const int64_t sample = p.sample_begin + slot;
 
-    // 1. initial values and child counts; every parent must be a node
+    // 1. initial values (no children, size 1, own degree) and child counts;
+    // every parent must be a node
     if (tid == 0) bad = 0;
     for (int64_t a = tid; a < n; a += kSpanThreads) {
-        s.cnt[a] = 0;
-        s.acc[a] = 0;
-        s.sz[a] = 1;
+        s.cs[a] = 1ull;
         s.psd[a] = (int64_t)nbr_deg(p.nbr[a]);
+        s.acc[a] = 0;
     }
     span_sync();
     for (int64_t u = tid; u < n; u += kSpanThreads)
@@ -100,73 +118,78 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
                 raise_err(p.err, kErrInconsistent, -10);
                 bad = 1;
             } else {
-                add32(&s.cnt[nx], 1);
+                add_wg(&s.cs[nx], 1ull << 32);
             }
         }
     span_sync();
     if (bad) return;   // the same LDS value for every thread after the barrier
     // the leaves, fixed before any count is consumed
-    for (int64_t u = tid; u < n; u += kSpanThreads) s.s0[u] = ld_acq32(&s.cnt[u]);
+    for (int64_t u = tid; u < n; u += kSpanThreads) s.leaf[u] = (int32_t)(ld_wg(&s.cs[u]) >> 32);
     span_sync();
 
     // 2. bottom-up sums: leaves climb; the last child at a parent continues
+    // with the parent's final size (from its atomic) and degree sum
     for (int64_t u = tid; u < n; u += kSpanThreads) {
-        if (u == root || s.s0[u] != 0) continue;
-        int32_t a = (int32_t)u;
+        if (u == root || s.leaf[u] != 0) continue;
         int32_t za = 1;
-        int64_t pa = (int64_t)nbr_deg(p.nbr[a]);
+        int64_t pa = (int64_t)nbr_deg(p.nbr[u]);
+        int32_t par = st_next(st[u]);
         for (int64_t guard = 0; guard < n; ++guard) {
-            const int32_t par = st_next(st[a]);
-            add32(&s.sz[par], za);
-            add64(&s.psd[par], pa);
-            const int32_t before =
-                __hip_atomic_fetch_add(&s.cnt[par], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (before != 1 || par == root) break;
-            a = par;
-            za = ld_acq32(&s.sz[a]);
-            pa = ld_acq64(&s.psd[a]);
+            add_wg(&s.psd[par], pa);
+            // size += za and count -= 1 in one word; release: the degree sum
+            // above is visible to whichever child arrives last
+            const uint64_t old = __hip_atomic_fetch_add(&s.cs[par], (uint64_t)(uint32_t)za - (1ull << 32),
+                                                        __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if ((old >> 32) != 1ull || par == root) break;
+            za += cs_size(old);
+            const int32_t a = par;
+            pa = ld_wg(&s.psd[a]);
+            par = st_next(st[a]);
         }
     }
     span_sync();
 
-    // 3. sibling offsets (stored in cnt, now all zero)
+    // 3. sibling offsets
     for (int64_t u = tid; u < n; u += kSpanThreads)
         if (u != root)
-            s.cnt[u] = __hip_atomic_fetch_add(&s.acc[st_next(st[u])], ld_acq32(&s.sz[u]), __ATOMIC_RELAXED,
+            s.off[u] = __hip_atomic_fetch_add(&s.acc[st_next(st[u])], cs_size(ld_wg(&s.cs[u])), __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_WORKGROUP);
     span_sync();
 
-    // 4. pre-order numbers: S[u] = 1 + offset, U[u] = parent (v: 0 and v),
-    // doubled until every U is v; S then holds pre[u]
-    int32_t *S0 = s.s0, *S1 = s.s1, *U0 = s.u0, *U1 = s.u1;
-    for (int64_t u = tid; u < n; u += kSpanThreads) {
-        S0[u] = (u == root) ? 0 : 1 + s.cnt[u];
-        U0[u] = (u == root) ? root : st_next(st[u]);
-    }
+    // 4. pre-order numbers: sum = 1 + offset, pointer = parent (v: 0 and v),
+    // jumped in place until every pointer is v; the sum is then pre[u]
+    for (int64_t u = tid; u < n; u += kSpanThreads)
+        st_wg(&s.su[u], (u == root) ? su_pack(0, root) : su_pack(1 + s.off[u], st_next(st[u])));
     for (int round = 0; round < 40; ++round) {
         if (tid == 0) flag = 0;
         __syncthreads();
         bool more = false;
-        for (int64_t u = tid; u < n; u += kSpanThreads) {
-            const int32_t up = U0[u];
-            S1[u] = S0[u] + S0[up];
-            const int32_t up2 = U0[up];
-            U1[u] = up2;
-            more |= (up2 != root);
+        for (int64_t base = tid; base < n; base += (int64_t)kSpanThreads * kJumpBatch) {
+            uint64_t mine[kJumpBatch], up[kJumpBatch];
+#pragma unroll
+            for (int q = 0; q < kJumpBatch; ++q) {
+                const int64_t u = base + (int64_t)q * kSpanThreads;
+                mine[q] = (u < n) ? ld_wg(&s.su[u]) : su_pack(0, root);
+            }
+#pragma unroll
+            for (int q = 0; q < kJumpBatch; ++q)
+                up[q] = (su_ptr(mine[q]) != root) ? ld_wg(&s.su[su_ptr(mine[q])]) : 0ull;
+#pragma unroll
+            for (int q = 0; q < kJumpBatch; ++q) {
+                const int64_t u = base + (int64_t)q * kSpanThreads;
+                if (u < n && su_ptr(mine[q]) != root) {
+                    const int32_t next = su_ptr(up[q]);
+                    st_wg(&s.su[u], su_pack(su_sum(mine[q]) + su_sum(up[q]), next));
+                    more |= (next != root);
+                }
+            }
         }
         if (more) flag = 1;
         __syncthreads();
         const int f = flag;
-        int32_t *t = S0;
-        S0 = S1;
-        S1 = t;
-        t = U0;
-        U0 = U1;
-        U1 = t;
         __syncthreads();
         if (!f) break;
     }
-    const int32_t *pre = S0;
 
     // 5. BFS-path pass, 6. sums
     const int32_t *bp = p.bfs_par;
@@ -174,13 +197,13 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
     unsigned long long *X2 = p.X2 ? p.X2 + span_block(sample, p.n_blocks, p.n_total) * n : nullptr;
     long long k1 = 0, k2 = 0;
     for (int64_t u = tid; u < n; u += kSpanThreads) {
-        const int32_t pu = pre[u];
+        const int32_t pu = su_sum(s.su[u]);
         int64_t x1 = 0, x2 = 0, x2d = 0;
         int32_t e1 = (int32_t)u;
         for (int hop = 0; hop < n && e1 != root; ++hop) {
             const int32_t e2 = bp[e1];
             if (st_next(st[e1]) == e2) {
-                const int32_t lo = pre[e1], sz = s.sz[e1];
+                const int32_t lo = su_sum(s.su[e1]), sz = cs_size(s.cs[e1]);
                 if (lo <= pu && pu < lo + sz) {
                     x1 += 1;
                     x2 += sz;
@@ -188,7 +211,7 @@ __global__ __launch_bounds__(kSpanThreads) void spantree_kernel(SpanParams p) {
                 }
             }
             if (e2 != root && st_next(st[e2]) == e1) {
-                const int32_t lo = pre[e2], sz = s.sz[e2];
+                const int32_t lo = su_sum(s.su[e2]), sz = cs_size(s.cs[e2]);
                 if (lo <= pu && pu < lo + sz) {
                     x1 -= 1;
                     x2 -= sz;
