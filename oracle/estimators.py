@@ -178,3 +178,12 @@ def pair_entries(V, omega, d_s, d_t):
     else:
         out["r_se"] = np.full(V.shape[1], np.nan)
     return out
+
+
+def lv_rows(Y, omega, deg, root):
+    """Rows of L_v^{-1} from loop-included path counts (Sec. 3.4):
+    (L_v^{-1})_{s u} = sum_b Y[b][j][u] / (omega d_u); column v is zero."""
+    tot = np.asarray(Y, np.int64).sum(0).astype(np.float64)
+    out = tot / (omega * np.asarray(deg, np.float64)[None, :])
+    out[:, root] = 0.0
+    return out

@@ -59,6 +59,8 @@ def lib():
         L.oracle_loop_included.restype = i32
         L.oracle_pair_paths.argtypes = [i64, P, P, i32, u64, u32, u64, i64, i64, i64, i32, i64, P, P, P, i32]
         L.oracle_pair_paths.restype = i32
+        L.oracle_lv_rows.argtypes = [i64, P, P, i32, u64, u32, u64, i64, i64, i64, i32, i64, P, P, i32]
+        L.oracle_lv_rows.restype = i32
         L.oracle_bfs_tree.argtypes = [i64, P, P, i32, P]
         L.oracle_bfs_tree.restype = i64
         L.oracle_spantree_tree.argtypes = [i64, P, i32, P, P, P, P, P, P, P]
@@ -275,3 +277,19 @@ def pair_paths(g, root, n_samples, seed, s, t, *, stream=0, qid=0, sample_begin=
     if st != 0:
         raise MemoryError("oracle_pair_paths failed")
     return V
+
+
+def lv_rows(g, root, n_samples, seed, sources, *, stream=0, qid=0, sample_begin=0, omega_total=None, B=1,
+            threads=0):
+    """Loop-included paths from each source through the stacks of each Wilson
+    sample: Y [B][n_sources][n] departures per node."""
+    n, rp, col = _graph(g)
+    if omega_total is None:
+        omega_total = sample_begin + n_samples
+    src = np.ascontiguousarray(sources, np.int32)
+    Y = np.zeros((B, len(src), n), np.int64)
+    st = lib().oracle_lv_rows(n, _p(rp), _p(col), int(root), seed, stream, qid, sample_begin, n_samples,
+                              omega_total, B, len(src), _p(src), _p(Y), threads)
+    if st != 0:
+        raise MemoryError("oracle_lv_rows failed")
+    return Y

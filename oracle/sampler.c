@@ -13,7 +13,8 @@
  *     start drawn from the stationary distribution (Alg. 4);
  *   - loop-included paths read from the stacks (Sec. 3.4, Fig. 1(d)).
  *   - loop-included paths from given node pairs, the counts behind entries of
- *     L_v^{-1} and effective resistances (Sec. 3.4, Sec. 2).
+ *     L_v^{-1} and effective resistances (Sec. 3.4, Sec. 2), and from given
+ *     sources, the counts behind whole rows of L_v^{-1}.
  * Random choices (the paper leaves the generator open):
  *   - generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11);
  *   - key = (seed, stream<<32 | root);
@@ -692,6 +693,65 @@ int32_t oracle_pair_paths(int64_t n, const int64_t *rp, const int32_t *col, int3
                         row[side ? 3 : 1] += there;
                         for (int64_t k = 0; k < nt; ++k) pos[touched[k]] = 0;
                     }
+                }
+            }
+        }
+        free(pos); free(touched);
+    }
+    return status;
+}
+
+/*
+ * Whole rows of L_v^{-1} from loop-included paths (Sec. 3.4): for sample i in
+ * [sample_begin, sample_begin + n_samples) and source j, the path from s_j
+ * through the stacks of sample i; every departure from a node u adds one to
+ * Y[b][j][u] ([B][n_sources][n], block b = floor(i*B/omega_total)).  Then
+ * (L_v^{-1})_{s_j u} is the expectation of Y[.][j][u] / d_u per sample.
+ */
+int32_t oracle_lv_rows(int64_t n, const int64_t *rp, const int32_t *col, int32_t root,
+                       uint64_t seed, uint32_t stream, uint64_t qid,
+                       int64_t sample_begin, int64_t n_samples, int64_t omega_total, int32_t B,
+                       int64_t n_sources, const int32_t *src, int64_t *Y, int32_t n_threads) {
+    if (B < 1) B = 1;
+    const uint64_t k0 = seed, k1 = make_key1(stream, root);
+    int32_t status = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        int64_t *pos = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+        int32_t *touched = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!pos || !touched) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            status = -1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+            for (int64_t q = 0; q < n_samples; ++q) {
+                const int64_t i = sample_begin + q;
+                const int64_t b = (int64_t)(((__int128)i * B) / omega_total);
+                draw_ctx dc;
+                memset(&dc, 0, sizeof dc);
+                dc.rp = rp; dc.col = col; dc.k0 = k0; dc.k1 = k1; dc.c0 = (uint64_t)i; dc.qid = qid;
+                for (int64_t j = 0; j < n_sources; ++j) {
+                    int64_t *row = Y + (b * n_sources + j) * n;
+                    int64_t nt = 0;
+                    int32_t u = src[j];
+                    while (u != root) {
+                        if (pos[u] == 0) touched[nt++] = u;
+                        const int32_t w = stack_entry(&dc, u, pos[u]);
+                        pos[u] += 1;
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                        row[u] += 1;
+                        u = w;
+                    }
+                    for (int64_t k = 0; k < nt; ++k) pos[touched[k]] = 0;
                 }
             }
         }

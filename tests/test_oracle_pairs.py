@@ -9,7 +9,10 @@ assembled from them (r(s,t) of Sec. 2):
 - every departure a path makes uses an entry that the Wilson sample drew;
 - the expectations against the dense grounded inverse and pseudo-inverse;
 - the closed forms of paths, cycles and complete graphs;
-- the exact identities of equal, swapped and root pairs, and sample splitting.
+- the exact identities of equal, swapped and root pairs, and sample splitting;
+- whole rows of L_v^{-1} (departures per node on the paths from given
+  sources): equal to the pair counts where both exist, exact on a star,
+  and against the dense grounded inverse and hitting times.
 """
 import math
 
@@ -143,3 +146,47 @@ def test_pair_identities_and_splitting():
     a = native.pair_paths(g, v, 40, 5, s, t, B=3, sample_begin=0, omega_total=omega)
     b = native.pair_paths(g, v, 56, 5, s, t, B=3, sample_begin=40, omega_total=omega)
     assert np.array_equal(a + b, V)
+
+
+def test_rows_agree_with_pair_paths_exactly():
+    """The row counts of the path from s at s and at t are the pair counts V0
+    and V1 of the pair (s, t) (two separately written oracle loops)."""
+    g = er256()
+    v = csr.landmark(g)
+    rng = np.random.default_rng(8)
+    s = rng.integers(0, g.n, 12)
+    t = rng.integers(0, g.n, 12)
+    s[0] = v
+    Y = native.lv_rows(g, v, 200, 6, s, B=4)
+    V = native.pair_paths(g, v, 200, 6, s, t, B=4)
+    j = np.arange(len(s))
+    assert np.array_equal(Y[:, j, s], V[:, :, 0]) and np.array_equal(Y[:, j, t], V[:, :, 1])
+    assert (Y[:, :, v] == 0).all() and (Y[:, 0, :] == 0).all()    # no departures from v; the row of v is zero
+
+
+def test_rows_star_and_dense_expectations():
+    g = graph("star", 7)
+    Y = native.lv_rows(g, 0, 50, 2, [3, 0])
+    assert Y[0, 0, 3] == 50 and Y[0, 0].sum() == 50 and Y[0, 1].sum() == 0
+    g = graph("barabasi_albert", 30, 2, 4)
+    v = csr.landmark(g)
+    L = dense.laplacian(g)
+    G = dense.walk_green(L, v)
+    src = np.array([0, 5, 17, 29])
+    omega, B = 1 << 14, 32
+    Y = native.lv_rows(g, v, omega, 3, src, B=B)
+    sizes = estimators.block_sizes(omega, B)
+    mean = Y.sum(0) / omega
+    se = (Y / sizes[:, None, None]).std(0, ddof=1) / math.sqrt(B)
+    live = se > 0
+    z = (mean[live] - G[src][live]) / se[live]
+    assert np.abs(z).max() < 5.0 and (np.abs(z) < 3).mean() > 0.97
+    assert np.array_equal(G[src] == 0, mean == 0)
+    # row sums are path lengths: their expectation is the hitting time of v
+    h = G[src].sum(1)
+    tot = Y.sum(2)                                     # [B][sources]
+    zt = (tot.sum(0) / omega - h) / ((tot / sizes[:, None]).std(0, ddof=1) / math.sqrt(B))
+    assert np.abs(zt).max() < 4.0
+    est = estimators.lv_rows(Y, omega, g.deg, v)
+    Lvi = dense.lv_inv(L, v)
+    np.testing.assert_allclose(est, Lvi[src], rtol=0.1, atol=0.02)
