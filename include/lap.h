@@ -348,6 +348,25 @@ int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int32_t *ps, co
                    int64_t n_pairs, int32_t check, int64_t lanes, int64_t *V, double *r, double *r_se,
                    double *lv, void *hip_stream);
 
+/*
+ * lap_lv_rows -- whole rows of L_v^{-1} from loop-included paths of the
+ * Wilson stacks (Sec. 3.4, the loop-erased-walk interpretation of L_v^{-1}):
+ * for every sample i of a and source j, the path from s_j through the stacks
+ * of sample i, taking at its c-th departure from u the entry S_i[u][c]
+ * (Philox counter (i, u, c, qid)), until it reaches v.  Every departure from
+ * u adds one to the source's row at u; (L_v^{-1})_{s_j u} is its expectation
+ * per sample over d_u.
+ *   sources [n_sources] node ids (host), 1 <= n_sources <= 2^23; a source may
+ *           be v (its row is zero).
+ *   check, lanes  as for lap_pair_paths.
+ * Outputs (host unless LAP_OUT_DEVICE; either may be NULL):
+ *   Y     int64 [B][n_sources][n] departures per node, per sample block (exact);
+ *   rows  [n_sources][n] sum over blocks of Y / (omega d_u), 0 in column v.
+ * B * n_sources * n must stay within 2^33.  Scratch as for lap_pair_paths.
+ */
+int lap_lv_rows(lap_graph *g, const lap_sample_args *a, const int32_t *sources, int64_t n_sources,
+                int32_t check, int64_t lanes, int64_t *Y, double *rows, void *hip_stream);
+
 /* ---------------------------------------------------------------- serving */
 
 /*
@@ -444,8 +463,8 @@ const char *lap_last_error(void);
  * bracketed by HIP events on the stream it runs on; lap_prof_read returns
  * the accumulated milliseconds and launch count for a kernel name
  * ("wilson_wave", "wilson_lane", "wilson_group", "spantree", "loop_included",
- * "pair_paths", "pair_assemble", "absorbed", "assemble", "batch",
- * "batch_assemble").  Returns
+ * "pair_paths", "pair_assemble", "lv_rows", "absorbed", "assemble",
+ * "batch", "batch_assemble").  Returns
  * LAP_EINVAL for an unknown name. */
 int lap_prof_enable(int on);
 int lap_prof_reset(void);

@@ -234,6 +234,20 @@ class Graph:
                                                   _ptr(se), _stream(stream)))
         return tr, se
 
+    def lv_rows(self, sources, omega, seed, root=-1, *, B=1, check=True, lanes=0, sample_begin=0, n_total=0,
+                mode=0, pool=0, group=0, stream_id=0, qid=0, timeout_s=0.0, stream=None):
+        """Whole rows of L_v^{-1} from loop-included paths (lap_lv_rows):
+        Y [B][n_sources][n] departures per node, rows [n_sources][n]."""
+        src = np.ascontiguousarray(sources, np.int32)
+        if src.ndim != 1:
+            raise ValueError("sources must be a 1-D array")
+        a = self._args(omega, seed, root, 0, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s,
+                       group=group)
+        out = dict(Y=np.zeros((B, len(src), self.n), np.int64), rows=np.zeros((len(src), self.n)))
+        _check(load_library().lap_lv_rows(self._h, ctypes.byref(a), _ptr(src), len(src), int(bool(check)), int(lanes),
+                                          _ptr(out["Y"]), _ptr(out["rows"]), _stream(stream)))
+        return out
+
     def last_stats(self):
         vals = [ctypes.c_int64() for _ in range(8)]
         _check(load_library().lap_last_stats(self._h, *[ctypes.byref(v) for v in vals]))

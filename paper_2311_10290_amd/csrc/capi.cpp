@@ -726,23 +726,16 @@ int ready_lanes(DevBuf &words_buf, DevBuf &tags_buf, int64_t &ready, int64_t lan
 
 }  // namespace
 
-extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int32_t *ps, const int32_t *pt,
-                              int64_t n_pairs, int32_t check, int64_t lanes, int64_t *V, double *r_out,
-                              double *r_se, double *lv, void *hip_stream) {
-    if (!g) return fail(LAP_EINVAL, "graph is NULL");
-    if (n_pairs < 1 || n_pairs > kPairMaxPairs) return fail(LAP_EINVAL, "n_pairs must be in [1, 2^23]");
-    if (!ps || !pt) return fail(LAP_EINVAL, "pair arrays are NULL");
-    if (check != 0 && check != 1) return fail(LAP_EINVAL, "check must be 0 or 1");
-    if (lanes < 0) return fail(LAP_EINVAL, "lanes must be >= 0");
-    Resolved r;
-    int rc = resolve_args(g, a, 0, nullptr, r);
-    if (rc != LAP_OK) return rc;
+namespace {
+
+// The launches of lap_pair_paths (rows null: paths from s_j and from t_j,
+// sums into pair_v) and of lap_lv_rows (rows given: one path from each s_j,
+// departures per node into rows).  d_ids holds s (and t) on the device.
+int pair_run(lap_graph *g, const Resolved &r, const lap_sample_args *a, const int32_t *d_ids, int64_t n_pairs,
+             unsigned long long *rows, int32_t check, int64_t lanes, hipStream_t s, Timer &tm) {
+    int rc = LAP_OK;
     const int64_t n = g->csr.n;
-    for (int64_t j = 0; j < n_pairs; ++j)
-        if (ps[j] < 0 || ps[j] >= n || pt[j] < 0 || pt[j] >= n) return fail(LAP_EINVAL, "pair node out of range");
-    hipStream_t s = (hipStream_t)hip_stream;
-    Timer tm;
-    const int64_t paths = 2 * n_pairs;
+    const int64_t paths = rows ? n_pairs : 2 * n_pairs;
     const int64_t hash_words = (int64_t)1 << kPairHashLog2;
     // Lanes in flight: bounded by the counter budget and by `lanes`.  Graphs
     // with more nodes than a table has words use the hashed form first.
@@ -754,15 +747,9 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
     const int64_t dense_cap = lane_cap(std::max<int64_t>(n, 1));
     const int64_t hash_cap = lane_cap(hash_words);
     bool hashed = n > hash_words;
-    const size_t vwords = (size_t)r.B * n_pairs * 4;
-    if (g->pair_ids.ensure(sizeof(int32_t) * (size_t)paths) || g->pair_v.ensure(sizeof(uint64_t) * vwords) ||
-        g->pair_out.ensure(sizeof(double) * (size_t)n_pairs * 5) || g->pair_next.ensure(sizeof(uint64_t) * 128) ||
+    if (g->pair_next.ensure(sizeof(uint64_t) * 128) || g->pair_v.ensure(sizeof(uint64_t) * 4) ||
         g->err.ensure(sizeof(DevErr)) || g->stats.ensure(sizeof(uint64_t) * kNumStats))
         return fail(LAP_ENOMEM, "cannot allocate pair path workspace");
-    int32_t *d_ids = g->pair_ids.as<int32_t>();
-    HIP_TRY(hipMemcpyAsync(d_ids, ps, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_ids + n_pairs, pt, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_fill_u64(g->pair_v.as<uint64_t>(), 0ull, (int64_t)vwords, s));
     const double tmo = a->timeout_s > 0 ? a->timeout_s : 120.0;
     int64_t acc[kNumStats] = {0};
     int64_t queued_total = 0, hashed_items = 0;
@@ -818,6 +805,7 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
         p.n_total = r.total;
         p.n_blocks = r.B;
         p.V = g->pair_v.as<unsigned long long>();
+        p.rows = rows;
         p.stats = g->stats.as<unsigned long long>();
         p.err = g->err.as<DevErr>();
         p.deadline = (uint64_t)(tmo * g->clock_khz * 1000.0);
@@ -867,6 +855,36 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
         done += chunk;
     }
     for (int i = 0; i < kNumStats; ++i) g->last_stats[i] = acc[i];
+    return LAP_OK;
+}
+
+}  // namespace
+
+extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int32_t *ps, const int32_t *pt,
+                              int64_t n_pairs, int32_t check, int64_t lanes, int64_t *V, double *r_out,
+                              double *r_se, double *lv, void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (n_pairs < 1 || n_pairs > kPairMaxPairs) return fail(LAP_EINVAL, "n_pairs must be in [1, 2^23]");
+    if (!ps || !pt) return fail(LAP_EINVAL, "pair arrays are NULL");
+    if (check != 0 && check != 1) return fail(LAP_EINVAL, "check must be 0 or 1");
+    if (lanes < 0) return fail(LAP_EINVAL, "lanes must be >= 0");
+    Resolved r;
+    int rc = resolve_args(g, a, 0, nullptr, r);
+    if (rc != LAP_OK) return rc;
+    const int64_t n = g->csr.n;
+    for (int64_t j = 0; j < n_pairs; ++j)
+        if (ps[j] < 0 || ps[j] >= n || pt[j] < 0 || pt[j] >= n) return fail(LAP_EINVAL, "pair node out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Timer tm;
+    const size_t vwords = (size_t)r.B * n_pairs * 4;
+    if (g->pair_ids.ensure(sizeof(int32_t) * (size_t)(2 * n_pairs)) || g->pair_v.ensure(sizeof(uint64_t) * vwords) ||
+        g->pair_out.ensure(sizeof(double) * (size_t)n_pairs * 5))
+        return fail(LAP_ENOMEM, "cannot allocate pair path workspace");
+    int32_t *d_ids = g->pair_ids.as<int32_t>();
+    HIP_TRY(hipMemcpyAsync(d_ids, ps, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_ids + n_pairs, pt, sizeof(int32_t) * n_pairs, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u64(g->pair_v.as<uint64_t>(), 0ull, (int64_t)vwords, s));
+    if ((rc = pair_run(g, r, a, d_ids, n_pairs, nullptr, check, lanes, s, tm)) != LAP_OK) return rc;
     double *d = g->pair_out.as<double>();
     PairAsmParams q;
     q.nbr = g->nbr.as<uint64_t>();
@@ -886,6 +904,44 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
         (rc = copy_out(r_out, d, sizeof(double) * n_pairs, s)) ||
         (rc = copy_out(r_se, d + n_pairs, sizeof(double) * n_pairs, s)) ||
         (rc = copy_out(lv, d + 2 * n_pairs, sizeof(double) * 3 * n_pairs, s)))
+        return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    tm.collect();
+    return LAP_OK;
+}
+
+
+extern "C" int lap_lv_rows(lap_graph *g, const lap_sample_args *a, const int32_t *sources, int64_t n_sources,
+                           int32_t check, int64_t lanes, int64_t *Y, double *rows, void *hip_stream) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    if (n_sources < 1 || n_sources > kPairMaxPairs) return fail(LAP_EINVAL, "n_sources must be in [1, 2^23]");
+    if (!sources) return fail(LAP_EINVAL, "source array is NULL");
+    if (check != 0 && check != 1) return fail(LAP_EINVAL, "check must be 0 or 1");
+    if (lanes < 0) return fail(LAP_EINVAL, "lanes must be >= 0");
+    Resolved r;
+    int rc = resolve_args(g, a, 0, nullptr, r);
+    if (rc != LAP_OK) return rc;
+    const int64_t n = g->csr.n;
+    for (int64_t j = 0; j < n_sources; ++j)
+        if (sources[j] < 0 || sources[j] >= n) return fail(LAP_EINVAL, "source node out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Timer tm;
+    const int64_t ywords = (int64_t)r.B * n_sources * n;
+    if (ywords > ((int64_t)8 << 30)) return fail(LAP_ENOMEM, "B * n_sources * n exceeds 2^33 counts");
+    if (g->pair_ids.ensure(sizeof(int32_t) * (size_t)n_sources) || g->pair_rows.ensure(sizeof(uint64_t) * ywords) ||
+        g->pair_rows_out.ensure(sizeof(double) * (size_t)(n_sources * n)))
+        return fail(LAP_ENOMEM, "cannot allocate row workspace");
+    int32_t *d_ids = g->pair_ids.as<int32_t>();
+    HIP_TRY(hipMemcpyAsync(d_ids, sources, sizeof(int32_t) * n_sources, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u64(g->pair_rows.as<uint64_t>(), 0ull, ywords, s));
+    unsigned long long *Yd = g->pair_rows.as<unsigned long long>();
+    if ((rc = pair_run(g, r, a, d_ids, n_sources, Yd, check, lanes, s, tm)) != LAP_OK) return rc;
+    double *out = g->pair_rows_out.as<double>();
+    tm.begin("lv_rows", s);
+    HIP_TRY(launch_lv_rows(Yd, g->nbr.as<uint64_t>(), n, n_sources, r.B, r.omega, r.root, out, s));
+    tm.end(s);
+    if ((rc = copy_out(Y, Yd, sizeof(int64_t) * (size_t)ywords, s)) ||
+        (rc = copy_out(rows, out, sizeof(double) * (size_t)(n_sources * n), s)))
         return rc;
     HIP_TRY(hipStreamSynchronize(s));
     tm.collect();

@@ -90,6 +90,7 @@ struct lap_graph {
     // loop-included paths from node pairs: per-lane counter words and last
     // tags (dense and hashed forms; lanes set up so far), queue, counters
     lap::DevBuf pair_cnt, pair_cnt_tags, pair_tbl, pair_tbl_tags, pair_queue, pair_next, pair_ids, pair_v, pair_out;
+    lap::DevBuf pair_rows, pair_rows_out;   // lap_lv_rows: counts and rows
     int64_t pair_cnt_lanes = 0, pair_tbl_lanes = 0;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -99,7 +100,7 @@ struct lap_graph {
                           &keep_draws, &err, &stats, &asm_partial, &asm_sums, &asm_trace, &est_out, &blkcount,
                           &bfs_par, &span64, &span32, &span_x, &span_s, &loop_cnt, &loop_y2, &loop_len,
                           &pair_cnt, &pair_cnt_tags, &pair_tbl, &pair_tbl_tags, &pair_queue, &pair_next,
-                          &pair_ids, &pair_v, &pair_out};
+                          &pair_ids, &pair_v, &pair_out, &pair_rows, &pair_rows_out};
         for (lap::DevBuf *b : bufs) b->release();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);

@@ -51,6 +51,8 @@ int64_t span_assemble_parts(int64_t n);
 hipError_t launch_loop_included(const LoopParams &p, hipStream_t s);
 hipError_t launch_pair_paths(const PairParams &p, bool hashed, hipStream_t s);
 hipError_t launch_pair_assemble(const PairAsmParams &p, hipStream_t s);
+hipError_t launch_lv_rows(const unsigned long long *Y, const uint64_t *nbr, int64_t n, int64_t n_src, int32_t B,
+                          int64_t omega, int32_t root, double *out, hipStream_t s);
 hipError_t launch_serve(const ServeParams &p, int64_t waves, hipStream_t s);
 hipError_t launch_serve_group(const ServeParams &p, int waves, int64_t groups, hipStream_t s);
 hipError_t launch_batch(const BatchParams &p, int64_t waves, hipStream_t s);

@@ -111,7 +111,8 @@ struct LoopParams {
     uint64_t deadline;
 };
 
-// Loop-included paths from node pairs over the stacks of the launch's samples (loops.hip)
+// Loop-included paths from node pairs, or from sources for whole rows of L_v^{-1},
+// over the stacks of the launch's samples (loops.hip)
 struct PairParams {
     int64_t n;
     const uint64_t *nbr;
@@ -137,6 +138,8 @@ struct PairParams {
     int64_t sample_begin, n_total;
     int32_t n_blocks;
     unsigned long long *V;         // [B][n_pairs][4]
+    unsigned long long *rows;      // rows form: [B][n_pairs][n] departures per node of the paths from ps
+                                   // (one path per source; pt and V unused), or null
     unsigned long long *stats;
     DevErr *err;
     uint64_t deadline;

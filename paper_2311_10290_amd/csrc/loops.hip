@@ -62,7 +62,9 @@ hipError_t launch_loop_included(const LoopParams &p, hipStream_t s) {
 // u, divided by d_u, estimate (L_v^{-1})_su, and
 //   r(s,t) = (L_v^{-1})_ss + (L_v^{-1})_tt - 2 (L_v^{-1})_st.
 // Work item slot * 2 n_pairs + q: path q (q even: from s_j, odd: from t_j,
-// j = q / 2) through the stacks of sample sample_begin + slot.
+// j = q / 2) through the stacks of sample sample_begin + slot.  In the rows
+// form there is one path per source (item slot * n_pairs + j, from s_j), and
+// every departure from u adds one to the source's row at u instead.
 //
 // Path lengths spread widely, so a lane does not wait for the other lanes of
 // its wave: whenever its path ends it takes the next item, from one of
@@ -74,8 +76,9 @@ hipError_t launch_loop_included(const LoopParams &p, hipStream_t s) {
 //   hashed an open-addressing table of 2^hash_log2 words (node | tag << 32 |
 //          count << 48), probed linearly from a multiplicative hash; a path
 //          that meets more than hash_limit distinct nodes, or departs 2^16-1
-//          times from one node, is abandoned before it adds anything and
-//          queued for the dense form.
+//          times from one node, is abandoned and queued for the dense form
+//          (in the rows form, after its departures so far are taken back out
+//          of its row; the table holds exactly those).
 // A word belongs to the current path only if it carries the path's tag, so a
 // new path starts from zero by taking the lane's next tag; only when the tags
 // run out does a lane clear its own words.  Each lane's last tag persists in
@@ -97,6 +100,13 @@ struct DenseDepartures {
     __device__ __forceinline__ uint32_t get(int32_t u) const {
         const uint64_t e = w[u];
         return ((uint32_t)(e >> 32) == tag) ? (uint32_t)e : 0u;
+    }
+    // take the current path's departures back out of a row
+    __device__ void unwind(unsigned long long *row) const {
+        for (int64_t k = 0; k < words; ++k) {
+            const uint64_t e = w[k];
+            if ((uint32_t)(e >> 32) == tag && (uint32_t)e) atomicAdd(&row[k], 0ull - (unsigned long long)(uint32_t)e);
+        }
     }
     // count before this departure from u, or kDepFull
     __device__ __forceinline__ uint32_t bump(int32_t u) {
@@ -129,6 +139,13 @@ struct HashDepartures {
             if ((uint32_t)e == (uint32_t)u) return (uint32_t)(e >> 48);
         }
     }
+    // take the current path's departures back out of a row
+    __device__ void unwind(unsigned long long *row) const {
+        for (int64_t k = 0; k < words; ++k) {
+            const uint64_t e = w[k];
+            if (mine(e)) atomicAdd(&row[(uint32_t)e], 0ull - (unsigned long long)(e >> 48));
+        }
+    }
     __device__ __forceinline__ uint32_t bump(int32_t u) {
         for (uint32_t h = home(u);; h = (h + 1) & mask) {
             const uint64_t e = w[h];
@@ -150,7 +167,7 @@ struct HashDepartures {
 template <class Dep>
 __device__ void pair_lane(const PairParams &p, Dep &dep, int64_t lane) {
     const int64_t n = p.n;
-    const int64_t paths = 2 * p.n_pairs;
+    const int64_t paths = p.rows ? p.n_pairs : 2 * p.n_pairs;
     const int part = (int)(blockIdx.x % (unsigned)p.n_parts);
     const int64_t n_items = p.queue_in ? (int64_t)*p.queue_in_len : p.n_items;
     const int64_t lo = n_items * part / p.n_parts, hi = n_items * (part + 1) / p.n_parts;
@@ -165,14 +182,17 @@ __device__ void pair_lane(const PairParams &p, Dep &dep, int64_t lane) {
     bool from_t = false;
     const uint64_t *st = nullptr;
     uint32_t ep = 0;
+    unsigned long long *row = nullptr;   // rows form: the current path's row
     for (;;) {
-        if (u == p.root && item >= 0) {
+        if (u == p.root && item >= 0 && p.rows) {
+            item = -1;   // rows form: the departures went to the row as they happened
+        } else if (u == p.root && item >= 0) {
             // the path reached v: add its departures from s_j and t_j (the root never departs)
             const unsigned long long here = (from != p.root) ? dep.get(from) : 0u;
             const unsigned long long there = (other != p.root) ? dep.get(other) : 0u;
-            unsigned long long *row = p.V + (((i * (int64_t)p.n_blocks) / p.n_total) * p.n_pairs + j) * 4;
-            if (here) atomicAdd(&row[from_t ? 2 : 0], here);
-            if (there) atomicAdd(&row[from_t ? 3 : 1], there);
+            unsigned long long *vrow = p.V + (((i * (int64_t)p.n_blocks) / p.n_total) * p.n_pairs + j) * 4;
+            if (here) atomicAdd(&vrow[from_t ? 2 : 0], here);
+            if (there) atomicAdd(&vrow[from_t ? 3 : 1], there);
             item = -1;
         }
         const bool need = (u == p.root);
@@ -190,10 +210,17 @@ __device__ void pair_lane(const PairParams &p, Dep &dep, int64_t lane) {
                 i = p.sample_begin + slot;
                 st = p.state ? p.state + slot * n : nullptr;
                 ep = st ? p.slot_epoch[slot] : 0u;
-                j = q >> 1;
-                from_t = (q & 1) != 0;
-                from = from_t ? p.pt[j] : p.ps[j];
-                other = from_t ? p.ps[j] : p.pt[j];
+                if (p.rows) {
+                    j = q;
+                    from_t = false;
+                    from = other = p.ps[j];
+                    row = p.rows + (((i * (int64_t)p.n_blocks) / p.n_total) * p.n_pairs + j) * n;
+                } else {
+                    j = q >> 1;
+                    from_t = (q & 1) != 0;
+                    from = from_t ? p.pt[j] : p.ps[j];
+                    other = from_t ? p.ps[j] : p.pt[j];
+                }
                 if (tag == Dep::kTagMax) {   // tags used up: clear this lane's words
                     dep.clear();
                     tag = 0;
@@ -212,6 +239,8 @@ __device__ void pair_lane(const PairParams &p, Dep &dep, int64_t lane) {
                 raise_err(p.err, kErrDrawOverflow, -22);
                 break;
             }
+            // rows form: the departures so far already went to the row
+            if (row) dep.unwind(row);
             const unsigned long long at = atomicAdd(p.queue_out_len, 1ull);
             p.queue_out[at] = (unsigned long long)item;   // capacity: every item of the launch
             item = -1;
@@ -222,6 +251,7 @@ __device__ void pair_lane(const PairParams &p, Dep &dep, int64_t lane) {
             raise_err(p.err, kErrInconsistent, -21);
             break;
         }
+        if (row) atomicAdd(&row[u], 1ull);
         const uint64_t x = philox_w0((uint64_t)i, (uint64_t)u, (uint64_t)c, p.qid, p.k0, p.k1);
         u = p.col[nbr_off(nb) + (int64_t)pick_below(x, nbr_deg(nb))];
         ++steps;
@@ -306,6 +336,30 @@ __global__ __launch_bounds__(64) void pair_assemble_kernel(PairAsmParams p) {
         p.lv[3 * j + 1] = ((double)a[1] / dt + (double)a[3] / ds) / (2.0 * om);
         p.lv[3 * j + 2] = (double)a[2] / (om * dt);
     }
+}
+
+// Whole rows: (L_v^{-1})_{s_j u} = sum over blocks of the departures from u
+// on the paths from s_j, over (omega d_u); column v stays zero.
+__global__ __launch_bounds__(256) void lv_rows_kernel(const unsigned long long *Y, const uint64_t *nbr, int64_t n,
+                                                      int64_t n_src, int32_t B, int64_t omega, int32_t root,
+                                                      double *out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_src * n; e += stride) {
+        const int64_t u = e % n;
+        unsigned long long a = 0;
+        for (int b = 0; b < B; ++b) a += Y[(int64_t)b * n_src * n + e];
+        out[e] = (u == root) ? 0.0 : (double)a / ((double)omega * (double)nbr_deg(nbr[u]));
+    }
+}
+
+hipError_t launch_lv_rows(const unsigned long long *Y, const uint64_t *nbr, int64_t n, int64_t n_src, int32_t B,
+                          int64_t omega, int32_t root, double *out, hipStream_t s) {
+    const int64_t total = n_src * n;
+    if (total <= 0) return hipSuccess;
+    int64_t grid = (total + 255) / 256;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(lv_rows_kernel, dim3((unsigned)grid), dim3(256), 0, s, Y, nbr, n, n_src, B, omega, root, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_pair_assemble(const PairAsmParams &p, hipStream_t s) {

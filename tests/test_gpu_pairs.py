@@ -1,8 +1,9 @@
-"""Loop-included paths from node pairs on the GPU against the oracle: the
-per-block departure sums V are bit-exact (the same stack entries are read),
-with and without the Wilson run that checks every entry was drawn, in every
-sampler form; the FP64 entries and resistances agree to 1e-12 and sit within
-their standard errors of the dense truth."""
+"""Loop-included paths from node pairs and from sources on the GPU against the
+oracle: the per-block departure sums V and the row counts Y are bit-exact (the
+same stack entries are read), with and without the Wilson run that checks
+every entry was drawn, in every sampler form; the FP64 entries, rows and
+resistances agree to 1e-12 and sit within their standard errors of the dense
+truth."""
 import numpy as np
 import pytest
 
@@ -130,6 +131,48 @@ def test_pair_paths_tables_that_fill_up_bit_exact():
             _same(og, got, s, t, omega, 3, 4, root)
 
 
+def _same_rows(og, got, src, omega, seed, B, root):
+    exp = native.lv_rows(og, root, omega, seed, src, B=B)
+    assert np.array_equal(got["Y"], exp)
+    np.testing.assert_allclose(got["rows"], estimators.lv_rows(exp, omega, og.deg, root), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("mode,group", [(2, 0), (3, 4), (1, 0)])
+def test_lv_rows_small_graphs_bit_exact(mode, group):
+    for name, n, src, dst in small_cases():
+        og, hg = both(n, src, dst)
+        for root in sorted({0, csr.landmark(og), og.n - 1}):
+            srcs = np.array(sorted({0, root, og.n - 1, og.n // 2}), np.int32)
+            for check in (1, 0):
+                log(f"rows {name} root {root} mode {mode} check {check}")
+                got = hg.lv_rows(srcs, 90, 5, root, B=3, check=check, mode=mode, group=group, pool=7)
+                _same_rows(og, got, srcs, 90, 5, 3, root)
+
+
+def test_lv_rows_mid_workload_and_full_tables_bit_exact():
+    """Rows on the mid workload (hashed tables) and on an Erdos-Renyi graph
+    of 30,000 nodes where about a quarter of the paths outgrow their table:
+    their departures are taken back out of the row before the dense form
+    runs them again."""
+    import graphgen as gg
+    n, src, dst = ba_edges(100_000, 5, 0)
+    og, hg = both(n, src, dst)
+    root = csr.landmark(og)
+    srcs = np.array([root, 0, 1, 77, 5000, 99_999], np.int32)
+    for check, lanes in ((1, 0), (0, 0), (0, 300)):
+        log(f"rows ba100k check {check} lanes {lanes}")
+        got = hg.lv_rows(srcs, 64, 1, root, B=4, check=check, lanes=lanes)
+        _same_rows(og, got, srcs, 64, 1, 4, root)
+    src, dst = gg.erdos_renyi(30_000, 8 / 30_000, 2)
+    og, hg = both(30_000, src, dst, keep_lcc=True)
+    root = csr.landmark(og)
+    srcs = np.random.default_rng(3).integers(0, og.n, 8).astype(np.int32)
+    for check, lanes in ((0, 0), (1, 97)):
+        log(f"rows er30k check {check} lanes {lanes}")
+        got = hg.lv_rows(srcs, 16, 3, root, B=2, check=check, lanes=lanes)
+        _same_rows(og, got, srcs, 16, 3, 2, root)
+
+
 def test_pair_paths_argument_errors():
     from paper_2311_10290_amd import LapError
     n, src, dst = er256_edges()
@@ -144,3 +187,7 @@ def test_pair_paths_argument_errors():
         hg.pair_paths([0], [1], 10, 1, lanes=-1)
     with pytest.raises(ValueError):
         hg.pair_paths([0, 1], [1], 10, 1)
+    with pytest.raises(LapError):
+        hg.lv_rows([], 10, 1)
+    with pytest.raises(LapError):
+        hg.lv_rows([256], 10, 1)
