@@ -262,7 +262,8 @@ def bench_pairs(lap, g, root, n, omega=1024, n_pairs=256):
     """Resistances and grounded-inverse entries of node pairs from
     loop-included paths (Sec. 3.4) on the mid workload: 256 random pairs
     (seed 3), 1024 samples, B = 64; the entries read without the sampler
-    (check 0), then with the Wilson run that checks them (check 1)."""
+    (check 0), then with the Wilson run that checks them (check 1); then
+    whole rows of L_v^{-1} for 64 of the sources."""
     rng = np.random.default_rng(3)
     s = rng.integers(0, n, n_pairs).astype(np.int32)
     t = rng.integers(0, n, n_pairs).astype(np.int32)
@@ -284,6 +285,19 @@ def bench_pairs(lap, g, root, n, omega=1024, n_pairs=256):
     ok = r["r"] > 0
     out["median_rel_se_r"] = float(np.median(r["r_se"][ok] / r["r"][ok]))
     out["mean_path_len"] = out["check0"]["path_steps"] / out["paths"]
+    # whole rows of L_v^{-1} for 64 of the sources, same samples
+    src = s[:64]
+    g.lv_rows(src, omega, 1, root, check=0)
+    lap.prof_reset()
+    lap.prof_enable(True)
+    t0 = time.perf_counter()
+    g.lv_rows(src, omega, 1, root, check=0)
+    dt = time.perf_counter() - t0
+    lap.prof_enable(False)
+    ms, _ = lap.prof_read("pair_paths")
+    st = g.last_stats()
+    out["rows"] = {"sources": len(src), "s": dt, "path_kernel_ms": ms, "path_steps": st["absorbed_steps"],
+                   "path_steps_per_s": st["absorbed_steps"] / (ms * 1e-3)}
     return out
 
 

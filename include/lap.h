@@ -295,6 +295,23 @@ int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, double *diag, 
                           double *kemeny, double *kemeny_se, void *hip_stream);
 
 /*
+ * lap_spantree_sample_bound -- the Hoeffding sample sizes of the SpanTree
+ * analysis (Thm. 3 for Alg. 1, Thm. 4 for Alg. 3): with D the depth of the
+ * BFS tree from v (the longest path a flow is sent along),
+ *   kind 1 (closeness): omega >= 32 D^2 ln(2n / p_fail) / eps^2 gives
+ *          |estimate - (L^dagger)_uu| <= eps for all u with probability at
+ *          least 1 - p_fail;
+ *   kind 2 (Kemeny):    omega >= 8 m^2 D^2 ln(2 / p_fail) / eps^2 gives
+ *          |estimate - kappa| <= eps with probability at least 1 - p_fail
+ *          (m undirected edges).
+ * root = -1: the max-degree node.  Writes the bound, rounded up, to *omega
+ * (a double: the bounds outgrow 64-bit integers quickly) and D to *depth
+ * (either may be NULL).  Host only: no device work.
+ */
+int lap_spantree_sample_bound(const lap_graph *g, int32_t root, int32_t kind, double eps, double p_fail,
+                              double *omega, int32_t *depth);
+
+/*
  * lap_loop_included -- loop-included paths of the Wilson stacks (Sec. 3.4,
  * the loop-erased-walk interpretation of L_v^{-1}): for every sample i of a,
  * the path that starts where absorbed walk i of kind tag starts (1: uniform

@@ -20,7 +20,7 @@ EXPORTS = [
     "lap_bench_gather",
     "lap_batch_create", "lap_batch_job_info", "lap_batch_run", "lap_batch_autotune", "lap_batch_result",
     "lap_batch_stats", "lap_batch_free", "lap_landmark_traces", "lap_spantree", "lap_spantree_estimate",
-    "lap_loop_included", "lap_pair_paths", "lap_lv_rows",
+    "lap_loop_included", "lap_pair_paths", "lap_lv_rows", "lap_spantree_sample_bound",
     "lap_server_create", "lap_server_submit", "lap_server_step", "lap_server_poll", "lap_server_pending",
     "lap_server_globals", "lap_server_free",
 ]
@@ -122,6 +122,7 @@ def declare(lib):
         "lap_loop_included": ([P, ctypes.POINTER(SampleArgs), i32, P, P, P], i32),
         "lap_pair_paths": ([P, ctypes.POINTER(SampleArgs), P, P, i64, i32, i64, P, P, P, P, P], i32),
         "lap_lv_rows": ([P, ctypes.POINTER(SampleArgs), P, i64, i32, i64, P, P, P], i32),
+        "lap_spantree_sample_bound": ([P, i32, i32, ctypes.c_double, ctypes.c_double, P, P], i32),
         "lap_server_create": ([P, ctypes.POINTER(ServerConfig), P, P], i32),
         "lap_server_submit": ([P, ctypes.POINTER(Query)], i32),
         "lap_server_step": ([P, i32], i32),

@@ -248,6 +248,15 @@ class Graph:
                                           _ptr(out["Y"]), _ptr(out["rows"]), _stream(stream)))
         return out
 
+    def spantree_sample_bound(self, kind, eps, p_fail, root=-1):
+        """Hoeffding sample size of Thm. 3 (kind 1, closeness) or Thm. 4 (kind 2,
+        Kemeny) and the BFS depth it uses (lap_spantree_sample_bound)."""
+        w = ctypes.c_double()
+        d = ctypes.c_int32()
+        _check(load_library().lap_spantree_sample_bound(self._h, int(root), int(kind), float(eps), float(p_fail),
+                                                        ctypes.byref(w), ctypes.byref(d)))
+        return w.value, d.value
+
     def last_stats(self):
         vals = [ctypes.c_int64() for _ in range(8)]
         _check(load_library().lap_last_stats(self._h, *[ctypes.byref(v) for v in vals]))

@@ -948,6 +948,41 @@ extern "C" int lap_lv_rows(lap_graph *g, const lap_sample_args *a, const int32_t
     return LAP_OK;
 }
 
+// ------------------------------------------------ SpanTree sample bounds
+extern "C" int lap_spantree_sample_bound(const lap_graph *g, int32_t root, int32_t kind, double eps, double p_fail,
+                                         double *omega, int32_t *depth) {
+    if (!g) return fail(LAP_EINVAL, "graph is NULL");
+    const int64_t n = g->csr.n;
+    if (root < -1 || root >= n) return fail(LAP_EINVAL, "root out of range");
+    if (kind != 1 && kind != 2) return fail(LAP_EINVAL, "kind must be 1 (closeness) or 2 (Kemeny)");
+    if (!(eps > 0.0) || !(p_fail > 0.0) || !(p_fail < 1.0)) return fail(LAP_EINVAL, "need eps > 0 and 0 < p_fail < 1");
+    const int32_t v = root < 0 ? g->max_deg_node : root;
+    // depth of the BFS tree from v: the longest BFS path any flow is sent along
+    std::vector<int32_t> dist((size_t)n, -1), queue;
+    queue.reserve((size_t)n);
+    dist[v] = 0;
+    queue.push_back(v);
+    int32_t D = 0;
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const int32_t a = queue[h];
+        D = std::max(D, dist[a]);
+        for (int64_t j = g->csr.rp[a]; j < g->csr.rp[a + 1]; ++j) {
+            const int32_t b = g->csr.col[j];
+            if (dist[b] < 0) {
+                dist[b] = dist[a] + 1;
+                queue.push_back(b);
+            }
+        }
+    }
+    const double m = 0.5 * (double)g->csr.rp[n];
+    const double d2 = (double)D * (double)D;
+    const double w = (kind == 1) ? 32.0 * d2 * std::log(2.0 * (double)n / p_fail) / (eps * eps)
+                                 : 8.0 * m * m * d2 * std::log(2.0 / p_fail) / (eps * eps);
+    if (omega) *omega = std::ceil(w);
+    if (depth) *depth = D;
+    return LAP_OK;
+}
+
 static lap_sample_args default_args(int32_t root, int64_t omega, uint64_t seed, int32_t B) {
     lap_sample_args a;
     std::memset(&a, 0, sizeof a);

@@ -104,3 +104,38 @@ def test_spantree_argument_errors():
         hg.spantree(0, 1)
     with pytest.raises(LapError):
         hg.spantree(10, 1, root=999)
+
+
+def test_spantree_sample_bounds():
+    """Thm. 3 and Thm. 4 sample sizes: the BFS depth from v against the
+    oracle's BFS tree, and the two bounds on a path, a star and the small ER
+    workload."""
+    import math
+    from paper_2311_10290_amd import LapError
+    import graphgen as gg
+    cases = [("path", 9, gg.path(9)), ("star", 7, gg.star(7))]
+    n, s, d = er256_edges()
+    cases.append(("er256", n, (s, d)))
+    for name, n, (s, d) in cases:
+        og, hg = both(n, s, d)
+        root = csr.landmark(og)
+        par = native.bfs_tree(og, root)
+        depth = 0
+        for u in range(og.n):
+            k, x = 0, u
+            while x != root:
+                x = int(par[x])
+                k += 1
+            depth = max(depth, k)
+        m = og.nnz / 2
+        w1, d1 = hg.spantree_sample_bound(1, 0.05, 0.01)
+        w2, d2 = hg.spantree_sample_bound(2, 10.0, 0.1, root=root)
+        assert d1 == d2 == depth, name
+        assert w1 == math.ceil(32 * depth ** 2 * math.log(2 * og.n / 0.01) / 0.05 ** 2)
+        assert w2 == math.ceil(8 * m * m * depth ** 2 * math.log(2 / 0.1) / 10.0 ** 2)
+    with pytest.raises(LapError):
+        hg.spantree_sample_bound(3, 0.1, 0.1)
+    with pytest.raises(LapError):
+        hg.spantree_sample_bound(1, 0.0, 0.1)
+    with pytest.raises(LapError):
+        hg.spantree_sample_bound(1, 0.1, 1.0)
