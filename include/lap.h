@@ -345,9 +345,11 @@ int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t tag, int64
  *           order independence of the stacks this never happens);
  *           0: read the same entries without running the sampler (identical
  *           results, no Wilson work).
- *   lanes   paths in flight, each with n 8-byte departure counters; 0 picks
- *           min(2^17, 32 GiB / (8 n), the number of paths); a smaller value
- *           caps it (the results do not depend on it).
+ *   lanes   paths in flight; 0 picks up to 2^17 within 32 GiB of departure
+ *           counters per lane: a 16384-word hash table on graphs of more
+ *           than 16384 nodes (a path that meets more than 12288 distinct
+ *           nodes is rerun with n words), n words otherwise.  A positive
+ *           value caps it; the results do not depend on it.
  * Outputs (host unless LAP_OUT_DEVICE; any may be NULL):
  *   V     int64 [B][n_pairs][4] per sample block: departures from s on the
  *         path from s, from t on the path from s, from t on the path from t,
@@ -357,9 +359,9 @@ int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t tag, int64
  *   lv    [n_pairs][3] (L_v^{-1})_ss, (L_v^{-1})_st, (L_v^{-1})_tt with
  *         the off-diagonal entry averaged over both orders:
  *         V0/(omega d_s), (V1/d_t + V3/d_s)/(2 omega), V2/(omega d_t).
- * Scratch: 8 bytes per node per lane in flight, plus the Wilson state when
- * check is 1.  Walk steps are reported by lap_last_stats
- * as absorbed steps.
+ * Scratch: the lanes' counters (at most 32 GiB per form), 8 bytes per
+ * path of a launch for the rerun queue, and the Wilson state when check is
+ * 1.  Walk steps are reported by lap_last_stats as absorbed steps.
  */
 int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int32_t *ps, const int32_t *pt,
                    int64_t n_pairs, int32_t check, int64_t lanes, int64_t *V, double *r, double *r_se,
