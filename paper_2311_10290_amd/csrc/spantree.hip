@@ -36,7 +36,7 @@ namespace lap {
 
 constexpr int kSpanThreads = 256;
 constexpr int kSpanWave = 64;
-constexpr int kJumpBatch = 4;   // nodes whose jumps one thread has in flight
+constexpr int kJumpBatch = 8;   // nodes whose jumps one thread has in flight
 
 struct SpanScratch {
     int64_t *psd;    // degree sums of subtrees
