@@ -23,6 +23,7 @@ HBM_PEAK_GBS = 8000.0
 WILSON_BYTES_PER_STEP = 33.0     # offsets 16 + column 4 + draw count 8 + next 4 + tree flag 1
 RETRACE_BYTES_PER_NODE = 5.0
 LOADS_PER_WILSON_STEP = 3        # dependent random loads per draw: column, target state, target offsets
+CHASE_BYTES_PER_LOAD = 128       # FETCH_SIZE per 4 GiB pointer-chase load, measured on the gather benchmark
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_wave_traffic.json")
@@ -39,15 +40,18 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per Wilson launch from the committed counter summary, if it
-    was taken on the current kernel sources; otherwise null."""
+def measured_traffic(part="bytes_per_launch"):
+    """HBM bytes per Wilson launch (or its FETCH_SIZE part) from the committed
+    counter summary, if it was taken on the current kernel sources; otherwise
+    null."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    return t["bytes_per_launch"] if t.get("kernel_hash") == kernel_hash() else None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t["bytes_per_launch"] if part == "bytes_per_launch" else t["FETCH_SIZE"]["bytes"]
 
 
 def write_traffic(pmc_dir):
@@ -598,6 +602,13 @@ def main():
                          "peak_loads_per_s": peaks,
                          "frac_of_chase_peak_4GiB": achieved_loads / peaks["4GiB"]["chase"],
                          "state_bytes": 8 * g.n * min(omega, 4096)}
+        # line fetches: every 4 GiB chase load fetches one 128-byte line
+        # (FETCH_SIZE); the kernel's fetched bytes come from its counter summary
+        fetch = measured_traffic("FETCH_SIZE")
+        chase_line = peaks["4GiB"]["chase"] * CHASE_BYTES_PER_LOAD
+        res["gather"]["chase_line_bytes_per_s_4GiB"] = chase_line
+        res["gather"]["wilson_fetch_bytes_per_s"] = fetch / (wave_ms * 1e-3) if fetch else None
+        res["gather"]["frac_of_chase_line_rate"] = fetch / (wave_ms * 1e-3) / chase_line if fetch else None
     if not args.no_spantree:
         log("spantree")
         res["spantree"] = bench_spantree(lap, g, root, 1024)
