@@ -108,3 +108,37 @@ def test_random_pair_paths_bit_exact(case):
     exp = native.pair_paths(og, root, omega, seed, ps, pt, stream=stream, qid=qid, sample_begin=begin,
                             omega_total=total, B=B)
     assert np.array_equal(got["V"], exp)
+
+
+@pytest.mark.parametrize("case", range(9))
+def test_random_lv_rows_bit_exact(case):
+    """Whole rows (lap_lv_rows) on random graphs, roots, sources, seeds, ids,
+    block counts, sample ranges, lane caps, sampler forms and both check
+    settings: the row counts equal the oracle's."""
+    rng = np.random.default_rng(7000 + case)
+    n, s, d, lcc = _pair_graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=lcc)
+    large = og.n > 16384
+    root = int(rng.integers(0, og.n)) if (case % 4 and not large) else csr.landmark(og)
+    k = int(rng.integers(1, 12))
+    src = rng.integers(0, og.n, k).astype(np.int32)
+    src[0] = root if k > 1 else src[0]
+    omega = int(rng.integers(1, 30))
+    begin = int(rng.integers(0, 5))
+    total = begin + omega + int(rng.integers(0, 5))
+    B = int(rng.integers(1, min(total, 4) + 1))
+    seed = int(rng.integers(1 << 62))
+    stream = int(rng.integers(0, 4))
+    qid = int(rng.integers(0, 1 << 40))
+    mode, group = [(1, 0), (2, 0), (3, 2), (3, 4), (3, 8)][case % 5]
+    check = (case + 1) % 2
+    lanes = [0, 1, 7, 64, 1000][int(rng.integers(0, 5))]
+    if large:
+        lanes = max(lanes, 64)
+    log(f"random rows case {case}: n={og.n} root={root} sources={k} omega={omega} begin={begin} "
+        f"mode={mode}/{group} check={check} lanes={lanes}")
+    got = hg.lv_rows(src, omega, seed, root, B=B, check=check, lanes=lanes, sample_begin=begin, n_total=total,
+                     mode=mode, group=group, stream_id=stream, qid=qid)
+    exp = native.lv_rows(og, root, omega, seed, src, stream=stream, qid=qid, sample_begin=begin,
+                         omega_total=total, B=B)
+    assert np.array_equal(got["Y"], exp)
