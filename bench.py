@@ -494,7 +494,7 @@ def main():
     ap.add_argument("--no-pairs", action="store_true")
     ap.add_argument("--no-kc-families", action="store_true")
     ap.add_argument("--kc-n", type=int, default=100_000)
-    ap.add_argument("--serve-queries", type=int, default=300)
+    ap.add_argument("--serve-queries", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
     ap.add_argument("--write-traffic", metavar="DIR",

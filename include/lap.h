@@ -445,7 +445,7 @@ typedef struct {
     uint32_t stream;
     int64_t global_samples;  /* samples for the cached global terms; 0 = 256 */
     int64_t arena_bytes;     /* device memory for query results; 0 = 64 MiB */
-    int32_t launches;        /* launches in flight (streams); 0 = 3 */
+    int32_t launches;        /* launches in flight (streams); 0 = 5 */
     int32_t waves;           /* wavefronts (Wilson state slots) per launch; 0 = 4 per CU */
     int32_t items_per_launch;/* 0 = 4096 */
     int32_t wilson_chunk;    /* Wilson samples per work item; 0 = 1 */

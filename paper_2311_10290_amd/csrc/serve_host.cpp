@@ -339,7 +339,7 @@ extern "C" int lap_server_create(lap_graph *g, const lap_server_config *cfg, voi
     if (c.root < 0) c.root = g->max_deg_node;
     if (c.global_samples == 0) c.global_samples = 256;
     if (c.arena_bytes == 0) c.arena_bytes = (int64_t)64 << 20;
-    if (c.launches == 0) c.launches = 3;
+    if (c.launches == 0) c.launches = 5;
     if (c.waves == 0) c.waves = 4 * g->n_cu;
     if (c.items_per_launch == 0) c.items_per_launch = 4096;
     if (c.wilson_chunk == 0) c.wilson_chunk = 1;
