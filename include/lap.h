@@ -447,7 +447,7 @@ typedef struct {
     int64_t arena_bytes;     /* device memory for query results; 0 = 64 MiB */
     int32_t launches;        /* launches in flight (streams); 0 = 5 */
     int32_t waves;           /* wavefronts (Wilson state slots) per launch; 0 = 4 per CU */
-    int32_t items_per_launch;/* 0 = 4096 */
+    int32_t items_per_launch;/* 0 = 4096; a Wilson-only launch takes at most `waves` items */
     int32_t wilson_chunk;    /* Wilson samples per work item; 0 = 1 */
     double timeout_s;        /* kernel time limit; 0 = 300 s */
     int32_t wilson_group;    /* wavefronts per Wilson sample in Wilson launches: 1 = wave form,

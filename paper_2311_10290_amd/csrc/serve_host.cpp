@@ -265,8 +265,23 @@ int launch(lap_server *s, int idx) {
     SLaunch &L = s->launches[idx];
     const int cls = s->launches.size() < 2 ? 2 : (idx % 2);
     int64_t cnt = 0;
-    bool any = true;
     const double t = now_s(s->t0);
+    if (cls == 1) {
+        // Wilson launches: at most one sample per state slot, oldest query
+        // first, so that a launch lasts about one sample and the samples of a
+        // Kemeny query finish together in as few launches as possible
+        const int64_t cap = std::min<int64_t>(s->cfg.items_per_launch, s->cfg.waves);
+        for (auto &kv : s->active) {
+            SQuery &Q = kv.second;
+            while (cnt < cap && Q.issued < Q.n_items && next_item(s, Q, L.h_items[cnt], cls)) {
+                L.serials.push_back(kv.first);
+                if (Q.t_start < 0) Q.t_start = t;
+                ++cnt;
+            }
+            if (cnt >= cap) break;
+        }
+    }
+    bool any = cls != 1;
     while (any && cnt < s->cfg.items_per_launch) {
         any = false;
         for (auto &kv : s->active) {
