@@ -108,7 +108,7 @@ def cpu_baseline(og, root, omega_full, seed, budget_s=15.0):
         steps += int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
         reps += 1
         dt = time.perf_counter() - t
-        if n_s < omega_full or dt >= 0.6 * budget_s:
+        if n_s < omega_full or dt >= 0.7 * budget_s:
             break
     # one thread on a smaller sample: the per-core rate
     n1 = max(8, n_s // (2 * threads))
