@@ -142,3 +142,40 @@ def test_random_lv_rows_bit_exact(case):
     exp = native.lv_rows(og, root, omega, seed, src, stream=stream, qid=qid, sample_begin=begin,
                          omega_total=total, B=B)
     assert np.array_equal(got["Y"], exp)
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_batches_bit_exact(case):
+    """Batched launches (lap_batch_*) of random job lists: graph families and
+    sizes, roots, sample counts, seeds, stream and query ids, pools, chunk
+    sizes, eager or captured launches.  Every job's counts equal the oracle's
+    for that job alone."""
+    from paper_2311_10290_amd import Batch
+    rng = np.random.default_rng(9000 + case)
+    jobs, graphs = [], []
+    for j in range(int(rng.integers(1, 13))):
+        n, s, d, _ = _graph(rng, int(rng.integers(0, 4)))
+        og = csr.build_csr(n, s, d, keep_lcc=True)
+        root = -1 if rng.random() < 0.5 else int(rng.integers(0, og.n))
+        jobs.append(dict(n=n, src=s, dst=d, keep_lcc=True, root=root, omega=int(rng.integers(1, 200)),
+                         seed=int(rng.integers(1 << 62)), stream_id=int(rng.integers(0, 4)),
+                         qid=int(rng.integers(0, 1 << 40))))
+        graphs.append(og)
+    pool = [0, 1, 3, 64, 500][int(rng.integers(0, 5))]
+    chunk = [0, 1, 100, 5000, 1 << 20][int(rng.integers(0, 5))]
+    use_graph = bool(case % 2)
+    log(f"random batch case {case}: jobs={len(jobs)} pool={pool} chunk={chunk} graph={use_graph}")
+    b = Batch(jobs)
+    b.run(Batch.tuning(pool=pool, chunk_nodes=chunk, use_graph=use_graph))
+    for j, (job, og) in enumerate(zip(jobs, graphs)):
+        root = b.info[j]["root"]
+        assert b.info[j]["n"] == og.n and root == (job["root"] if job["root"] >= 0 else csr.landmark(og))
+        om, seed, sid, qid = job["omega"], job["seed"], job["stream_id"], job["qid"]
+        r = b.result(j)
+        w = native.wilson(og, root, om, seed, stream=sid, qid=qid)
+        a1 = native.absorbed(og, root, om, seed, 1, stream=sid, qid=qid)
+        a2 = native.absorbed(og, root, om, seed, 2, stream=sid, qid=qid, want_y2=False)
+        assert np.array_equal(r["Y1"], w["Y1"][0]) and np.array_equal(r["y1"], w["y1"]), j
+        assert np.array_equal(r["Y2"], a1["Y2"][0]) and np.array_equal(r["len_uniform"], a1["len"]), j
+        assert np.array_equal(r["len_pi"], a2["len"]), j
+    b.close()
