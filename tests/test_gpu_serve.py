@@ -115,3 +115,63 @@ def test_admission_by_result_memory():
     with pytest.raises(LapError):
         srv.submit(999, 0, 301, u=1)                      # can never fit
     srv.close()
+
+
+def _random_graph(rng, case):
+    kind = case % 3
+    if kind == 0:
+        n = int(rng.integers(40, 400))
+        s, d = gg.erdos_renyi(n, float(rng.uniform(3.0, 8.0)) / n, int(rng.integers(1 << 30)))
+    elif kind == 1:
+        n = int(rng.integers(40, 2000))
+        s, d = gg.barabasi_albert(n, int(rng.integers(1, 5)), int(rng.integers(1 << 30)))
+    else:
+        r, c = int(rng.integers(3, 25)), int(rng.integers(3, 25))
+        n = r * c
+        s, d = gg.grid(r, c)
+    return n, s, d
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_server_configs_match_oracle(case):
+    """Random graphs, roots and query mixes under random server configurations:
+    stream counts, slots per launch, items per launch, samples per Wilson item,
+    Kemeny forms and result arenas small enough to hold back admission.  Every
+    result and the cached global terms equal the oracle's."""
+    from paper_2311_10290_amd import Server
+    rng = np.random.default_rng(11000 + case)
+    n, s, d = _random_graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=True)
+    root = csr.landmark(og) if case % 2 == 0 else int(rng.integers(0, og.n))
+    qs, used = [], set()
+    for _ in range(int(rng.integers(4, 21))):
+        kind = int(rng.choice([0, 1, 2], p=[0.4, 0.4, 0.2]))
+        qid = int(rng.integers(0, 1 << 40))
+        while qid in used:
+            qid = int(rng.integers(0, 1 << 40))
+        used.add(qid)
+        budget = int(rng.integers(1, 65 if kind == 2 else 301))
+        u = root if rng.random() < 0.1 else int(rng.integers(0, og.n))
+        w = int(rng.integers(0, og.n))
+        qs.append(dict(qid=qid, kind=kind, u=u, w=w, budget=budget))
+    words = max((4 if q["kind"] == 1 else 2) * q["budget"] for q in qs)
+    cfg = dict(launches=int(rng.integers(1, 7)), waves=[0, 1, 3, 17, 64][int(rng.integers(0, 5))],
+               items_per_launch=[0, 1, 2, 7, 50][int(rng.integers(0, 5))],
+               wilson_chunk=[0, 1, 3][int(rng.integers(0, 3))], wilson_group=[0, 1, 2, 4, 8][int(rng.integers(0, 5))],
+               arena_bytes=0 if rng.random() < 0.5 else 8 * words * int(rng.integers(1, 4)))
+    G = int(rng.integers(16, 257))
+    log(f"random serve case {case}: n={og.n} root={root} queries={len(qs)} cfg={cfg}")
+    srv = Server(hg, seed=SEED, root=root, global_samples=G, **cfg)
+    for q in qs:
+        srv.submit(q["qid"], q["kind"], q["budget"], q["u"], q["w"])
+    res = {r["qid"]: r for r in srv.run_all(timeout_s=120)}
+    tr_lv, s_lv = srv.globals()
+    srv.close()
+    assert len(res) == len(qs) and all(r["status"] == 0 for r in res.values())
+    w = native.wilson(og, root, G, SEED, qid=GLOBAL_QID)
+    a = native.absorbed(og, root, G, SEED, 1, qid=GLOBAL_QID)
+    otr, os_ = estimators.globals_from_counts(w["Y1"][0], a["Y2"][0], G, og.deg, root)
+    np.testing.assert_allclose([tr_lv, s_lv], [otr, os_], rtol=1e-12)
+    for q in qs:
+        want = _oracle_value(og, root, q, tr_lv, s_lv)
+        np.testing.assert_allclose(res[q["qid"]]["value"], want, rtol=1e-12, err_msg=str(q))
