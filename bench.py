@@ -147,12 +147,13 @@ def bench_batch(lap, gg, n_jobs):
         s, d = gg.job_edges(sp)
         jobs.append(dict(n=sp["n"], src=s, dst=d, keep_lcc=True, root=-1, omega=sp["omega"], seed=1))
     log(f"batch: generated {n_jobs} graphs in {time.perf_counter() - t0:.1f} s")
-    # autotune on every 8th job (a probe batch of the same mix), run all jobs
-    probe = lap.Batch(jobs[::8])
-    tuning, tune_ms = probe.autotune()
-    probe.close()
+    # autotune on the whole batch (a probe subset of the jobs favours smaller
+    # pools than the whole batch runs best with), then time the tuned batch
     b = lap.Batch(jobs)
-    log(f"batch: autotuned pool={tuning.pool} chunk={tuning.chunk_nodes} ({tune_ms:.1f} ms)")
+    t_tune = time.perf_counter()
+    tuning, tune_ms = b.autotune()
+    log(f"batch: autotuned pool={tuning.pool} chunk={tuning.chunk_nodes} ({tune_ms:.1f} ms per run, "
+        f"{time.perf_counter() - t_tune:.1f} s of tuning)")
     b.run(tuning)
     torch.cuda.synchronize()
     reps = 3

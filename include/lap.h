@@ -233,7 +233,11 @@ int lap_batch_job_info(const lap_batch *b, int32_t job, int64_t *n, int64_t *nnz
  * captured once per tuning on an internal stream and replayed. */
 int lap_batch_run(lap_batch *b, const lap_batch_tuning *t, void *hip_stream);
 /* Time a grid of pool sizes (8, 16, 24 waves per CU) and chunk sizes (2^15,
- * 2^17, 2^19) on the whole batch and return the fastest (with use_graph set). */
+ * 2^17, 2^19) on the whole batch, after one untimed warm-up run, and return
+ * (with use_graph set) the largest pool among the tunings within 3% of the
+ * fastest, at its fastest chunk size; *best_ms is that tuning's time.  When
+ * the batch is a probe subset of a larger one, the larger pool is the safer
+ * pick there. */
 int lap_batch_autotune(lap_batch *b, lap_batch_tuning *best, double *best_ms, void *hip_stream);
 /* Copy one job's results of the last run to host buffers (NULL = skip). */
 int lap_batch_result(const lap_batch *b, int32_t job, lap_batch_out *out);

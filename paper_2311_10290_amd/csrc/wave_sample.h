@@ -21,7 +21,7 @@ constexpr int kClaimMask = (1 << kClaimBits) - 1;
 constexpr int kRevCap = 256;
 constexpr int kStackDepth = 12;
 constexpr uint32_t kStackMaxK = 255;
-constexpr int kScanChunks = 4;
+constexpr int kScanChunks = 2;
 
 enum : int32_t {
     kIdle = 0,
