@@ -20,7 +20,7 @@ Contents
 
 Parity status: every function is pinned by tests under ``tests/`` that check
 it against closed forms, the paper's worked examples, a library routine or
-brute force, except ``estimators.rw_betweenness`` (parity unpinned: the
-formula quoted at the end of Sec. 5 is implemented as printed, with no
-independent definition to check it against).
+brute force.  ``estimators.rw_betweenness`` implements the formula quoted at
+the end of Sec. 5 as printed; it is pinned by the closed forms on complete
+graphs and stars and by the same quantity rebuilt from pairwise resistances.
 """

@@ -51,8 +51,9 @@ def kirchhoff(diag):
 
 def rw_betweenness(diag):
     """1/n + Tr/((n-1)(Tr + n L^dagger_uu)), the formula quoted at the end of
-    Sec. 5.  Parity unpinned: no independent definition of this quantity is
-    implemented here; tests only check the HIP path against this formula."""
+    Sec. 5, as printed.  Pinned by closed forms (complete graphs, stars) and
+    by the identity Tr + n L^dagger_uu = sum_v r(u,v) on resistances from the
+    other pseudo-inverse route."""
     n = len(diag)
     tr = math.fsum(np.asarray(diag).tolist())
     return 1.0 / n + tr / ((n - 1) * (tr + n * np.asarray(diag)))

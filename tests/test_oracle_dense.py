@@ -135,3 +135,37 @@ def test_kirchhoff_index_closed_forms_and_trace_identity():
     for g in (graph("grid", 3, 4), graph("barabasi_albert", 30, 2, 7)):
         Ld = dense.pinv_eigh(dense.laplacian(g))
         assert estimators.kirchhoff(np.diag(Ld)) == pytest.approx(dense.kirchhoff_pairs(Ld), rel=1e-10)
+
+
+def test_rw_betweenness_closed_forms_and_farness_identity():
+    """The random-walk betweenness formula quoted at the end of Sec. 5,
+    c_b(u) = 1/n + Tr/((n-1)(Tr + n L^dagger_uu)), pinned without re-typing
+    it.  Tr + n L^dagger_uu is the farness sum_v r(u,v) and Tr is the
+    Kirchhoff index over n, so the formula is fixed by resistances alone:
+    - K_n: r = 2/n on every pair, farness 2(n-1)/n, Tr (n-1)/n, so
+      c_b = 1/n + 1/(2(n-1)) at every node;
+    - star with n nodes: centre-leaf r = 1, leaf-leaf r = 2, Tr (n-1)^2/n;
+      farness n-1 at the centre (c_b = 2/n) and 2n-3 at a leaf
+      (c_b = 1/n + (n-1)/(n(2n-3)));
+    - any graph: the value from the diagonal of the eigen-decomposition
+      pseudo-inverse equals 1/n + (Kf/n)/((n-1) farness(u)), with Kf and the
+      farness summed over resistances of the other route, (L + 11^T/n)^-1."""
+    from oracle import estimators
+    for n in (4, 7, 10):
+        Ld = dense.pinv_eigh(dense.laplacian(graph("complete", n)))
+        np.testing.assert_allclose(estimators.rw_betweenness(np.diag(Ld)), 1 / n + 1 / (2 * (n - 1)), rtol=1e-12)
+        g = graph("star", n)
+        Ld = dense.pinv_eigh(dense.laplacian(g))
+        cb = estimators.rw_betweenness(np.diag(Ld))
+        centre = int(np.argmax(g.deg))
+        want = np.full(n, 1 / n + (n - 1) / (n * (2 * n - 3)))
+        want[centre] = 2 / n
+        np.testing.assert_allclose(cb, want, rtol=1e-12)
+    for g in (graph("diamond"), graph("grid", 3, 4), graph("barabasi_albert", 30, 2, 7)):
+        n = g.n
+        L = dense.laplacian(g)
+        cb = estimators.rw_betweenness(np.diag(dense.pinv_eigh(L)))
+        Li = dense.pinv_inverse(L)
+        R = np.array([[dense.resistance(Li, s, t) for t in range(n)] for s in range(n)])
+        kf = R.sum() / 2
+        np.testing.assert_allclose(cb, 1 / n + (kf / n) / ((n - 1) * R.sum(1)), rtol=1e-10)
