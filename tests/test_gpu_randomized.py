@@ -179,3 +179,71 @@ def test_random_batches_bit_exact(case):
         assert np.array_equal(r["Y2"], a1["Y2"][0]) and np.array_equal(r["len_uniform"], a1["len"]), j
         assert np.array_equal(r["len_pi"], a2["len"]), j
     b.close()
+
+
+def _spantree_oracle(og, root, omega, seed, B, begin, total, stream, qid):
+    X1 = np.zeros((B, og.n), np.int64)
+    X2 = np.zeros((B, og.n), np.int64)
+    for b in range(B):
+        lo = max(begin, -(-b * total // B))
+        hi = min(begin + omega, -(-(b + 1) * total // B))
+        if hi > lo:
+            r = native.spantree(og, root, hi - lo, seed, 1, stream=stream, qid=qid, sample_begin=lo)
+            X1[b], X2[b] = r["X1"], r["X2"]
+    k = native.spantree(og, root, omega, seed, 2, stream=stream, qid=qid, sample_begin=begin)
+    return dict(X1=X1, X2=X2, s1=k["s1"], s2=k["s2"])
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_spantree_bit_exact(case):
+    """SpanTree sums (lap_spantree) on random graphs, roots, sample ranges,
+    block counts, seeds, stream and query ids, sampler forms and pools: the
+    per-block X1, X2 and the per-sample s1, s2 equal the oracle's."""
+    rng = np.random.default_rng(13100 + case)
+    n, s, d, lcc = _graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=lcc)
+    root = int(rng.integers(0, og.n)) if case % 3 else csr.landmark(og)
+    omega = int(rng.integers(1, 120))
+    begin = int(rng.integers(0, 5))
+    total = begin + omega + int(rng.integers(0, 5))
+    B = int(rng.integers(1, min(total, 6) + 1))
+    seed = int(rng.integers(1 << 62))
+    stream = int(rng.integers(0, 4))
+    qid = int(rng.integers(0, 1 << 40))
+    mode, group = [(1, 0), (2, 0), (3, 2), (3, 4), (3, 8)][case % 5]
+    pool = int(rng.integers(0, 40))
+    log(f"random spantree case {case}: n={og.n} root={root} omega={omega} begin={begin} B={B} "
+        f"mode={mode}/{group} pool={pool}")
+    got = hg.spantree(omega, seed, root, B=B, sample_begin=begin, n_total=total, mode=mode, group=group, pool=pool,
+                      stream_id=stream, qid=qid)
+    exp = _spantree_oracle(og, root, omega, seed, B, begin, total, stream, qid)
+    for k in ("X1", "X2", "s1", "s2"):
+        assert np.array_equal(got[k], exp[k]), k
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_loop_included_bit_exact(case):
+    """Loop-included paths (lap_loop_included) on random graphs, roots, start
+    kinds, sample ranges, block counts, seeds, ids, sampler forms and pools:
+    departures per node and per path equal the oracle's."""
+    rng = np.random.default_rng(15000 + case)
+    n, s, d, lcc = _graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=lcc)
+    root = int(rng.integers(0, og.n)) if case % 3 else csr.landmark(og)
+    tag = 1 + case % 2
+    omega = int(rng.integers(1, 150))
+    begin = int(rng.integers(0, 5))
+    total = begin + omega + int(rng.integers(0, 5))
+    B = int(rng.integers(1, min(total, 6) + 1))
+    seed = int(rng.integers(1 << 62))
+    stream = int(rng.integers(0, 4))
+    qid = int(rng.integers(0, 1 << 40))
+    mode, group = [(1, 0), (2, 0), (3, 2), (3, 4), (3, 8)][case % 5]
+    pool = int(rng.integers(0, 40))
+    log(f"random loops case {case}: n={og.n} root={root} tag={tag} omega={omega} begin={begin} B={B} "
+        f"mode={mode}/{group} pool={pool}")
+    got = hg.loop_included(omega, seed, tag, root, B=B, sample_begin=begin, n_total=total, mode=mode, group=group,
+                           pool=pool, stream_id=stream, qid=qid)
+    exp = native.loop_included(og, root, omega, seed, tag, stream=stream, qid=qid, sample_begin=begin,
+                               omega_total=total, B=B)
+    assert np.array_equal(got["Y2"], exp["Y2"]) and np.array_equal(got["len"], exp["len"])
