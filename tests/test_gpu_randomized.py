@@ -247,3 +247,42 @@ def test_random_loop_included_bit_exact(case):
     exp = native.loop_included(og, root, omega, seed, tag, stream=stream, qid=qid, sample_begin=begin,
                                omega_total=total, B=B)
     assert np.array_equal(got["Y2"], exp["Y2"]) and np.array_equal(got["len"], exp["len"])
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_estimates_match_oracle_assembly(case):
+    """FP64 estimates (lap_estimate, with the derived outputs) on random graphs,
+    roots, sample counts, block counts, seeds, ids and sampler forms: every
+    output equals the oracle's assembly of the oracle's counts to 1e-12
+    (standard errors to 1e-9)."""
+    from oracle import estimators
+    rng = np.random.default_rng(17100 + case)
+    n, s, d, lcc = _graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=lcc)
+    root = int(rng.integers(0, og.n)) if case % 3 else csr.landmark(og)
+    omega = int(rng.integers(2, 300))
+    B = int(rng.integers(1, min(omega, 8) + 1))
+    seed = int(rng.integers(1 << 62))
+    stream = int(rng.integers(0, 4))
+    qid = int(rng.integers(0, 1 << 40))
+    mode, group = [(1, 0), (2, 0), (3, 2), (3, 4), (3, 8)][case % 5]
+    log(f"random estimate case {case}: n={og.n} root={root} omega={omega} B={B} mode={mode}/{group}")
+    est = hg.estimate(omega, seed, root, B=B, lv=True, derived=True, mode=mode, group=group, stream_id=stream,
+                      qid=qid)
+    w = native.wilson(og, root, omega, seed, stream=stream, qid=qid, B=B)
+    a = native.absorbed(og, root, omega, seed, 1, stream=stream, qid=qid, B=B)
+    p = native.absorbed(og, root, omega, seed, 2, stream=stream, qid=qid, want_y2=False)
+    diag, se = estimators.diag_ldagger_blocks(w["Y1"], a["Y2"], omega, og.deg)
+    c, tr = estimators.closeness(diag)
+    k, kse = estimators.kemeny(w["y1"], p["len"])
+    np.testing.assert_allclose(est["diag"], diag, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(est["diag_se"], se, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(est["closeness"], c, rtol=1e-12)
+    np.testing.assert_allclose(est["trace"][0], tr, rtol=1e-12)
+    np.testing.assert_allclose(est["kemeny"][0], k, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(est["kemeny_se"][0], kse, rtol=1e-9, atol=1e-12)
+    lv = w["Y1"].sum(0) / (omega * og.deg)
+    lv[root] = 0.0
+    np.testing.assert_allclose(est["lv_diag"], lv, rtol=1e-12)
+    np.testing.assert_allclose(est["kirchhoff"][0], estimators.kirchhoff(diag), rtol=1e-12)
+    np.testing.assert_allclose(est["rw_betweenness"], estimators.rw_betweenness(diag), rtol=1e-12)
