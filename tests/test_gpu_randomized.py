@@ -286,3 +286,22 @@ def test_random_estimates_match_oracle_assembly(case):
     np.testing.assert_allclose(est["lv_diag"], lv, rtol=1e-12)
     np.testing.assert_allclose(est["kirchhoff"][0], estimators.kirchhoff(diag), rtol=1e-12)
     np.testing.assert_allclose(est["rw_betweenness"], estimators.rw_betweenness(diag), rtol=1e-12)
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_landmark_traces_bit_exact(case):
+    """Landmark study (lap_landmark_traces) on random graphs with random root
+    lists (repeats allowed) and sample counts: each root's mean draws equal
+    the oracle's per-sample totals for that root exactly."""
+    rng = np.random.default_rng(19000 + case)
+    n, s, d, lcc = _graph(rng, case)
+    og, hg = both(n, s, d, keep_lcc=lcc)
+    roots = rng.integers(0, og.n, int(rng.integers(1, 40))).astype(np.int32)
+    roots[0] = csr.landmark(og)
+    omega = int(rng.integers(1, 100))
+    seed = int(rng.integers(1 << 62))
+    log(f"random landmark case {case}: n={og.n} roots={len(roots)} omega={omega}")
+    tr, se = hg.landmark_traces(roots, omega, seed)
+    for j, r in enumerate(roots):
+        w = native.wilson(og, int(r), omega, seed, want_y1=False)
+        assert tr[j] == int(w["y1"].sum()) / omega, (j, int(r))
