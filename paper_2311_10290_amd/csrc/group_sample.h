@@ -24,7 +24,7 @@
 namespace lap {
 
 constexpr int kGroupRevCap = 1024;
-constexpr int kGroupScanChunks = 2;
+constexpr int kGroupScanChunks = 1;
 
 // claim table: about 32 slots per walker (a claim that shares its slot with
 // another node's retries next round), entries wide enough for a walker id
