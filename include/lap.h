@@ -47,8 +47,8 @@ typedef enum {
     LAP_ENOTCONN = -2,  /* graph not connected and LAP_KEEP_LCC not given (L_v singular) */
     LAP_ENOMEM = -3,    /* host or device allocation failed */
     LAP_EDEVICE = -4,   /* HIP runtime error, or no device */
-    LAP_ERANGE = -5     /* a count exceeded its field (e.g. 2^24 draws at one node in one
-                           sample) or a kernel passed its time limit */
+    LAP_ERANGE = -5     /* a count exceeded its field (e.g. more than 2^21 - 1 draws at one
+                           node in one sample) or a kernel passed its time limit */
 } lap_status;
 
 /* ------------------------------------------------------------------ graph */

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchParams p) {
             c.k1 = jb.k1;
             c.qid = jb.qid;
             c.st = st;
-            c.y1b = p.y1 + jb.node_off;
+            c.y1b = p.y1 ? p.y1 + jb.node_off : nullptr;
             c.keep_next = nullptr;
             c.keep_draws = nullptr;
             c.err = p.err;

@@ -35,6 +35,10 @@ struct lap_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     lap_batch_tuning exec_for{};
+    // what the captured launch baked into its kernel arguments: a replay is
+    // valid only while these are unchanged
+    const void *exec_items = nullptr, *exec_state = nullptr;
+    int64_t exec_n_items = 0;
     int64_t last_stats[kNumStats] = {0};
     ~lap_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -241,7 +245,7 @@ int finish(lap_batch *b, hipStream_t s, Timer &tm) {
     HIP_TRY(hipMemcpy(&e, b->err.ptr, sizeof e, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(st, b->stats.ptr, sizeof st, hipMemcpyDeviceToHost));
     for (int i = 0; i < kNumStats; ++i) b->last_stats[i] = (int64_t)st[i];
-    if (e.code == kErrDrawOverflow) return fail(LAP_ERANGE, "more than 2^24-1 draws at one node in one sample");
+    if (e.code == kErrDrawOverflow) return fail(LAP_ERANGE, "more than 2^21-1 draws at one node in one sample");
     if (e.code == kErrTimeout) return fail(LAP_ERANGE, "batch kernel time limit exceeded");
     if (e.code != kErrNone) return fail(LAP_EDEVICE, "walker state inconsistent");
     return LAP_OK;
@@ -257,10 +261,10 @@ extern "C" int lap_batch_run(lap_batch *b, const lap_batch_tuning *tin, void *hi
     int rc = build_items(b, t);
     if (rc != LAP_OK) return rc;
     if (t.pool > b->state_waves) {
-        if (b->exec) {
-            (void)hipGraphExecDestroy(b->exec);
-            b->exec = nullptr;
-        }
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
         if (b->state.ensure(8 * (size_t)t.pool * (size_t)b->max_n))
             return fail(LAP_ENOMEM, "cannot allocate walk state");
         b->state_waves = t.pool;
@@ -272,7 +276,10 @@ extern "C" int lap_batch_run(lap_batch *b, const lap_batch_tuning *tin, void *hi
             HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
             HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
         }
-        if (!b->exec || !same_shape(b->exec_for, t) || b->exec_for.use_graph != t.use_graph) {
+        // the item table is rebuilt (and may move) when the chunk size changes,
+        // and the walk state moves when the pool grows: capture again then
+        if (!b->exec || !same_shape(b->exec_for, t) || b->exec_for.use_graph != t.use_graph ||
+            b->exec_items != b->items_d.ptr || b->exec_state != b->state.ptr || b->exec_n_items != b->n_items) {
             if (b->exec) (void)hipGraphExecDestroy(b->exec);
             if (b->graph) (void)hipGraphDestroy(b->graph);
             b->exec = nullptr;
@@ -289,6 +296,9 @@ extern "C" int lap_batch_run(lap_batch *b, const lap_batch_tuning *tin, void *hi
             b->graph = g;
             HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
             b->exec_for = t;
+            b->exec_items = b->items_d.ptr;
+            b->exec_state = b->state.ptr;
+            b->exec_n_items = b->n_items;
         }
         HIP_TRY(hipEventRecord(b->ev_in, s));
         HIP_TRY(hipStreamWaitEvent(b->cap, b->ev_in, 0));
@@ -424,13 +434,13 @@ extern "C" int lap_landmark_traces(lap_graph *g, const int32_t *roots, int32_t n
         for (int64_t s = 0; s < omega; s += per) items.push_back({j, 0, s, std::min(per, omega - s)});
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t waves = std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), 16 * (int64_t)g->n_cu));
-    DevBuf d_jobs, d_items, d_counter, d_state, d_y1, d_y1s, d_err, d_stats;
+    DevBuf d_jobs, d_items, d_counter, d_state, d_y1s, d_err, d_stats;
     auto cleanup = [&]() {
-        DevBuf *b[] = {&d_jobs, &d_items, &d_counter, &d_state, &d_y1, &d_y1s, &d_err, &d_stats};
+        DevBuf *b[] = {&d_jobs, &d_items, &d_counter, &d_state, &d_y1s, &d_err, &d_stats};
         for (DevBuf *x : b) x->release();
     };
     if (d_jobs.ensure(sizeof(BatchJobDev) * jobs.size()) || d_items.ensure(sizeof(BatchItem) * items.size()) ||
-        d_counter.ensure(8) || d_state.ensure(8 * (size_t)waves * (size_t)n) || d_y1.ensure(8 * (size_t)n) ||
+        d_counter.ensure(8) || d_state.ensure(8 * (size_t)waves * (size_t)n) ||
         d_y1s.ensure(8 * (size_t)n_roots * (size_t)omega) || d_err.ensure(sizeof(DevErr)) ||
         d_stats.ensure(8 * kNumStats)) {
         cleanup();
@@ -446,8 +456,8 @@ extern "C" int lap_landmark_traces(lap_graph *g, const int32_t *roots, int32_t n
     p.col = g->col.as<int32_t>();
     p.state = d_state.as<uint64_t>();
     p.max_n = n;
-    p.y1 = d_y1.as<unsigned long long>();
-    p.y2 = d_y1.as<unsigned long long>();
+    p.y1 = nullptr;   // per-node counts are not needed: the trace is the per-sample total
+    p.y2 = nullptr;
     p.y1s = d_y1s.as<int64_t>();
     p.stats = d_stats.as<unsigned long long>();
     p.err = d_err.as<DevErr>();

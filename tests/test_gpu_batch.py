@@ -95,6 +95,30 @@ def test_batch_graph_replays():
                 assert np.array_equal(r[k], ref[j][k]), (rep, j, k)
 
 
+def test_batch_graph_recaptured_after_item_table_moves():
+    """A captured launch bakes in the item table's address and length.  An
+    eager run at a smaller chunk size grows (and so moves) the table; the
+    next captured run at the first chunk size must capture again instead of
+    replaying the old launch.  Every job equals the eager run bit for bit."""
+    from paper_2311_10290_amd import Batch
+    jobs = _jobs()
+    b = Batch(jobs)
+    keys = ("Y1", "Y2", "y1", "len_uniform", "len_pi", "diag", "closeness", "kemeny", "kemeny_se")
+    log("graph run, chunk 2^17")
+    b.run(Batch.tuning(chunk_nodes=1 << 17, use_graph=True))
+    first = [b.result(j) for j in range(len(jobs))]
+    log("eager run, chunk 2^15")
+    b.run(Batch.tuning(chunk_nodes=1 << 15, use_graph=False))
+    ref = [b.result(j) for j in range(len(jobs))]
+    log("graph run, chunk 2^17 again")
+    b.run(Batch.tuning(chunk_nodes=1 << 17, use_graph=True))
+    for j in range(len(jobs)):
+        r = b.result(j)
+        for k in keys:
+            assert np.array_equal(r[k], ref[j][k]), (j, k)
+            assert np.array_equal(first[j][k], ref[j][k]), (j, k)
+
+
 def test_batch_autotune_returns_a_working_tuning():
     from paper_2311_10290_amd import Batch
     jobs = _jobs()[:4]

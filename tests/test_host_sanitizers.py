@@ -1,7 +1,9 @@
-"""The threaded host CSR builder under AddressSanitizer + UBSan and under
-ThreadSanitizer (host code only: the harness makes no device call).  The
-harness compares every built graph with a plain sort-and-unique
-construction."""
+"""Host code under sanitizers (no device call anywhere):
+  - the threaded host CSR builder under AddressSanitizer + UBSan and under
+    ThreadSanitizer; the harness compares every built graph with a plain
+    sort-and-unique construction;
+  - the oracle's C sampler under AddressSanitizer + UBSan, every entry point
+    with one thread and several."""
 import os
 import subprocess
 
@@ -34,5 +36,22 @@ def test_csr_builder_under_sanitizers(tmp_path, san):
                            "-lamdhip64", f"-Wl,-rpath,{rocm}/lib", "-lpthread"])
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
+
+
+ORACLE = os.path.join(HERE, "..", "oracle", "sampler.c")
+
+
+@pytest.mark.skipif(not os.path.exists("/usr/bin/gcc"), reason="gcc not found")
+def test_oracle_sampler_under_address_and_ub_sanitizers(tmp_path):
+    """The oracle's C sampler (every entry point, one thread and several)
+    built with AddressSanitizer and UBSan; the harness checks tree shape and
+    count invariants and equal results across thread counts."""
+    exe = str(tmp_path / "oracle_check")
+    subprocess.check_call(["gcc", "-O1", "-g", "-fopenmp", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", os.path.join(HERE, "host", "oracle_check.c"), ORACLE,
+                           "-o", exe])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
