@@ -29,6 +29,14 @@ _lib = None
 def load_library():
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime.  Loaded first, it also serves
+        # liblap (same soname), so torch's streams and device tensors are
+        # valid in the library's calls; loaded after liblap, a second runtime
+        # would come up beside the first and could not see the device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(C.LIB_PATH):
             raise ImportError(f"{C.LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "or python paper_2311_10290_amd/build.py")
@@ -148,6 +156,37 @@ class Graph:
                      keep_idx=_ptr(keep) if nk else None, n_keep=nk,
                      next=_ptr(out["next"]), draws=_ptr(out["draws"]))
         _check(load_library().lap_sample_forests(self._h, ctypes.byref(a), ctypes.byref(c), _stream(stream)))
+        return out
+
+    def sample_forests_noalloc(self, omega, seed, root=-1, *, y1=True, y2=False, y2_pi=False, per_sample=True,
+                               B=1, keep=(), sample_begin=0, n_total=0, mode=0, pool=0, stream_id=0, qid=0,
+                               timeout_s=0.0, schedule=0, group=0, stream=None, out=None):
+        """lap_sample_forests_noalloc: the same counts as sample_forests, written
+        into caller-owned torch device tensors (``out``: Y1, Y2 [B, n], y1,
+        len_uniform, len_pi [omega], next, draws [len(keep), n]; int64 except
+        next/draws int32).  Without ``out`` the tensors are made here, before
+        the call.  Returns the dict of tensors."""
+        import torch
+        n = self.n
+        keep = np.ascontiguousarray(np.asarray(list(keep), np.int64))
+        nk = len(keep)
+        if out is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+            z = lambda *shape, dt=torch.int64: torch.zeros(*shape, dtype=dt, device=dev)
+            out = dict(Y1=z(B, n) if y1 else None, Y2=z(B, n) if y2 else None,
+                       y1=z(omega) if per_sample else None, len_uniform=z(omega) if y2 else None,
+                       len_pi=z(omega) if y2_pi else None,
+                       next=z(nk, n, dt=torch.int32) if nk else None, draws=z(nk, n, dt=torch.int32) if nk else None)
+        want = ((C.LAP_WANT_Y1 if y1 else 0) | (C.LAP_WANT_Y2_UNIFORM if y2 else 0)
+                | (C.LAP_WANT_Y2_PI if y2_pi else 0) | (C.LAP_WANT_PER_SAMPLE if per_sample else 0)
+                | C.LAP_OUT_DEVICE)
+        a = self._args(omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s,
+                       schedule, group)
+        c = C.Counts(y1=_ptr(out.get("Y1")), y2=_ptr(out.get("Y2")), y1_per_sample=_ptr(out.get("y1")),
+                     y2len_uniform=_ptr(out.get("len_uniform")), y2len_pi=_ptr(out.get("len_pi")),
+                     keep_idx=_ptr(keep) if nk else None, n_keep=nk,
+                     next=_ptr(out.get("next")), draws=_ptr(out.get("draws")))
+        _check(load_library().lap_sample_forests_noalloc(self._h, ctypes.byref(a), ctypes.byref(c), _stream(stream)))
         return out
 
     def estimate(self, omega, seed, root=-1, *, diag=True, se=True, lv=False, closeness=True, kemeny=True,
