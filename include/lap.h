@@ -142,6 +142,29 @@ typedef struct {
  */
 int lap_sample_forests(lap_graph *g, const lap_sample_args *a, lap_counts *out, void *hip_stream);
 
+/*
+ * lap_sample_forests_noalloc -- lap_sample_forests for callers that cannot
+ * allocate device memory: code under HIP graph capture, serving loops with a
+ * fixed device footprint, harnesses that forbid hipMalloc.  The call makes no
+ * hipMalloc or hipFree and calls no allocating library routine.
+ *   - Same arguments and the same counts as lap_sample_forests, except that
+ *     every output array in *out must be caller-owned DEVICE memory and a->want
+ *     must include LAP_OUT_DEVICE (else LAP_EINVAL).  keep_idx stays a host
+ *     array.  Absorbed walks run on the caller's stream after one another,
+ *     not on an auxiliary stream.
+ *   - Scratch (error word, statistics, block counts, slot epochs, walk state)
+ *     is one fixed 64 MiB device array per GPU, held until the process ends
+ *     and cleared by each call.  Concurrent samples are capped so that
+ *     slots x n state words fit it; results do not depend on the cap.
+ *   - Limits: n_blocks <= 4096 and, when Wilson samples are requested,
+ *     n <= 8,384,446 nodes; beyond them LAP_ERANGE and nothing runs.
+ *   - Calls that overlap on one GPU (from several host threads, or on several
+ *     streams) share that scratch and race: serialise them.
+ *   - The call is synchronous on hip_stream and must run on the device the
+ *     graph was built on.
+ */
+int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a, lap_counts *out, void *hip_stream);
+
 /* ------------------------------------------------------------- estimators */
 
 typedef struct {

@@ -15,7 +15,7 @@ LAP_MODE_AUTO, LAP_MODE_LANE, LAP_MODE_WAVE, LAP_MODE_GROUP = 0, 1, 2, 3
 # every symbol include/lap.h declares
 EXPORTS = [
     "lap_build_csr", "lap_graph_info", "lap_graph_copy_csr", "lap_graph_free",
-    "lap_sample_forests", "lap_estimate", "lap_diag_Ldagger", "lap_ecc", "lap_kemeny",
+    "lap_sample_forests", "lap_sample_forests_noalloc", "lap_estimate", "lap_diag_Ldagger", "lap_ecc", "lap_kemeny",
     "lap_last_error", "lap_prof_enable", "lap_prof_reset", "lap_prof_read", "lap_last_stats",
     "lap_bench_gather",
     "lap_batch_create", "lap_batch_job_info", "lap_batch_run", "lap_batch_autotune", "lap_batch_result",
@@ -99,6 +99,7 @@ def declare(lib):
         "lap_graph_copy_csr": ([P, P, P, P], i32),
         "lap_graph_free": ([P], None),
         "lap_sample_forests": ([P, ctypes.POINTER(SampleArgs), ctypes.POINTER(Counts), P], i32),
+        "lap_sample_forests_noalloc": ([P, ctypes.POINTER(SampleArgs), ctypes.POINTER(Counts), P], i32),
         "lap_estimate": ([P, ctypes.POINTER(SampleArgs), ctypes.POINTER(Estimates), P], i32),
         "lap_diag_Ldagger": ([P, i32, i64, u64, P, P, P], i32),
         "lap_ecc": ([P, i32, i64, u64, P, P, P], i32),

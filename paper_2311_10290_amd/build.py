@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblap.so")
 SOURCES = ["wilson.hip", "estimate.hip", "batch.hip", "gather_peak.hip", "common.cpp", "graph.cpp", "capi.cpp",
            "batch_host.cpp", "serve.hip", "serve_host.cpp", "spantree.hip",
-           "loops.hip"]
+           "loops.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LAP_OFFLOAD_ARCH", "gfx950")
 

@@ -129,14 +129,7 @@ extern "C" int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t
 }
 
 // --------------------------------------------------------------- sampling
-namespace {
-
-struct Resolved {
-    int64_t omega, begin, total;
-    int32_t root, B, mode, group;
-    int64_t slots;
-    bool wilson, y2u, y2p;
-};
+namespace lap {
 
 int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, const int64_t *keep_idx,
                  Resolved &r) {
@@ -192,6 +185,26 @@ int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, c
     r.slots = std::max<int64_t>(1, std::min({r.omega, pool, budget}));
     return LAP_OK;
 }
+
+int status_from_err(const DevErr &e) {
+    switch (e.code) {
+        case kErrNone:
+            return LAP_OK;
+        case kErrDrawOverflow:
+            if (e.detail == -22) return fail(LAP_ERANGE, "a node-pair path departed 2^32-1 times from one node");
+            return fail(LAP_ERANGE, "more than 2^21-1 draws at node " + std::to_string(e.detail) + " in one sample");
+        case kErrTimeout:
+            return fail(LAP_ERANGE, "kernel time limit exceeded");
+        default:
+            if (e.detail == -20 || e.detail == -21)
+                return fail(LAP_EDEVICE, "a loop-included path needed a stack entry its Wilson sample did not draw");
+            return fail(LAP_EDEVICE, "walker state inconsistent (tree count " + std::to_string(e.detail) + ")");
+    }
+}
+
+}  // namespace lap
+
+namespace {
 
 int ensure_state(lap_graph *g, int64_t slots, hipStream_t s) {
     const int64_t n = g->csr.n;
@@ -343,21 +356,7 @@ int finish(lap_graph *g, hipStream_t s, Timer &tm) {
     for (int i = 0; i < kNumStats; ++i) g->last_stats[i] = (int64_t)st[i];
     if (e.code != kErrNone) {
         g->state_dirty = true;
-        switch (e.code) {
-            case kErrDrawOverflow:
-                if (e.detail == -22)
-                    return fail(LAP_ERANGE, "a node-pair path departed 2^32-1 times from one node");
-                return fail(LAP_ERANGE, "more than 2^21-1 draws at node " + std::to_string(e.detail) +
-                                            " in one sample");
-            case kErrTimeout:
-                return fail(LAP_ERANGE, "kernel time limit exceeded");
-            default:
-                if (e.detail == -20 || e.detail == -21)
-                    return fail(LAP_EDEVICE, "a loop-included path needed a stack entry its Wilson sample did "
-                                             "not draw");
-                return fail(LAP_EDEVICE, "walker state inconsistent (tree count " +
-                                             std::to_string(e.detail) + ")");
-        }
+        return status_from_err(e);
     }
     return LAP_OK;
 }

@@ -32,6 +32,22 @@ int64_t bfs_parents(const HostCSR &g, int32_t root, std::vector<int32_t> &par);
 // Set the thread's error text and return code.
 int fail(int code, const std::string &msg);
 
+// Arguments of a sampling call, checked and resolved against the graph
+// (capi.cpp): sample range, landmark, blocks, sampler form and concurrent
+// sample slots.
+struct Resolved {
+    int64_t omega, begin, total;
+    int32_t root, B, mode, group;
+    int64_t slots;
+    bool wilson, y2u, y2p;
+};
+
+int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, const int64_t *keep_idx,
+                 Resolved &r);
+
+// Status and error text for a device-side error word (LAP_OK when clear).
+int status_from_err(const DevErr &e);
+
 #define HIP_TRY(expr)                                                                    \
     do {                                                                                 \
         hipError_t e_ = (expr);                                                          \
