@@ -301,6 +301,7 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         wp.n_slots = r.slots;   // lanes or waves taking part; <= allocated slots
         wp.nbr = g->nbr.as<uint64_t>();
         wp.col = g->col.as<int32_t>();
+        wp.arcs = (const ulonglong2 *)g->arcs.ptr;   // null below kArcsMinColBytes
         wp.root = r.root;
         wp.k0 = a->seed;
         wp.k1 = k1;

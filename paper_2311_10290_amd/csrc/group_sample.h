@@ -62,7 +62,7 @@ struct GroupShared {
     int64_t cut_at;
 };
 
-template <int W>
+template <int W, bool ARCS = false>
 static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<W> &sh, int64_t *y1_out,
                                            WaveStats &ws) {
     constexpr int NW = kWave * W;
@@ -105,6 +105,8 @@ static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<
     int32_t s = -1, h = -1, w = -1, x = -1, stop_at = -1, e = -1;
     uint32_t kh = 0, ke = 0;
     uint64_t nbh = 0, nbe = 0;
+    uint64_t nbw = 0;          // arc form: the target's adjacency record, when nbw_ok
+    bool nbw_ok = false;
     uint64_t it = 0;
     bool done = false;
 
@@ -142,7 +144,17 @@ static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<
             raise_err(c.err, kErrInconsistent, -1);
             sh.flag[par] = 1;
         }
-        const int32_t a_col = (la_col >= 0) ? c.col[la_col] : 0;
+        int32_t a_col = 0;
+        uint64_t a_nbw = 0;
+        if constexpr (ARCS) {
+            if (la_col >= 0) {
+                const ulonglong2 av = c.arcs[la_col];
+                a_col = (int32_t)av.x;
+                a_nbw = av.y;
+            }
+        } else {
+            a_col = (la_col >= 0) ? c.col[la_col] : 0;
+        }
         const uint64_t a_nb1 = (la_nb1 >= 0) ? c.nbr[la_nb1] : 0ull;
 
         // ==== B1: the previous round's stores, LDS writes and counters are visible
@@ -193,6 +205,7 @@ static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<
                 const int r = pre + __popcll(idle_m & below);
                 if (r < take) {
                     w = sh.rev[rev_n - 1 - r];
+                    nbw_ok = false;
                     mode = kArrive;
                     is_start = true;
                 }
@@ -203,6 +216,10 @@ static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<
         // ---- 2. finish draws: the drawn neighbour becomes the next target
         if (mode == kDraw) {
             w = a_col;
+            if constexpr (ARCS) {
+                nbw = a_nbw;
+                nbw_ok = true;
+            }
             if (kh >= kMaxDraws) {
                 raise_err(c.err, kErrDrawOverflow, h);
                 bad = true;
@@ -230,7 +247,7 @@ static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<
         int64_t lb_st = -1, lb_nb = -1;
         if (arriving) {
             lb_st = w;
-            lb_nb = w;
+            lb_nb = (ARCS && nbw_ok) ? -1 : w;
         } else if (!bad && (mode == kRetrace || mode == kRelease)) {
             lb_st = x;
         } else if (!bad && mode == kPopLoad) {
@@ -256,6 +273,16 @@ static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<
         }
 
         // ---- C. advance every walker by what its loads returned
+        if constexpr (ARCS) {
+            if (arriving) {
+                if (nbw_ok) {
+                    v_nb = nbw;
+                } else {
+                    nbw = v_nb;
+                    nbw_ok = true;
+                }
+            }
+        }
         bool claim = false, parked = false, push = false;
         int32_t wait_on = tid, pushed = -1;
         int rel_lo = 0, rel_hi = 0;
@@ -443,6 +470,8 @@ static __device__ bool group_wilson_sample(const WaveSampleArgs &c, GroupShared<
                     w = sh.cand_node[r];
                     v_st = sh.cand_st[r];
                     v_nb = sh.cand_nb[r];
+                    nbw = v_nb;
+                    nbw_ok = true;
                     mode = kArrive;
                     is_start = true;
                     claim = true;

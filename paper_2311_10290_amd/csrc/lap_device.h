@@ -93,6 +93,7 @@ struct WilsonParams {
     int64_t n_slots;       // sample slots allocated in state / slot_epoch
     const uint64_t *nbr;   // [n] packed offset/degree
     const int32_t *col;    // [2m]
+    const ulonglong2 *arcs;   // [2m] {target, target's adjacency record}, or null
     int32_t root;
     uint64_t k0, k1, qid;  // Philox key and counter word 3
     int64_t sample_begin, n_samples, n_total;
@@ -117,6 +118,7 @@ struct WaveSampleArgs {
     int64_t n, nnz;
     const uint64_t *nbr;
     const int32_t *col;
+    const ulonglong2 *arcs = nullptr;   // read instead of col by the arc form of the samplers
     int32_t root;
     uint64_t k0, k1, qid;
     int64_t sample;

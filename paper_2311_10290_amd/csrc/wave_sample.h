@@ -74,6 +74,7 @@ static __device__ __forceinline__ void wave_lds_sync() {
 // the scan loads the next candidate starts; (4) walkers act on what they
 // loaded; walkers that are idle now take free candidates from this round's
 // scan and claim them at once.
+template <bool ARCS = false>
 static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &sh, int64_t *y1_out, WaveStats &ws) {
     const int lane = (int)threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -106,6 +107,8 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
     int32_t s = -1, h = -1, w = -1, x = -1, stop_at = -1, e = -1;
     uint32_t kh = 0, ke = 0;
     uint64_t nbh = 0, nbe = 0;
+    uint64_t nbw = 0;          // arc form: the target's adjacency record, when nbw_ok
+    bool nbw_ok = false;
     uint64_t it = 0;
 
     // write the stack out as path words: entry j points to entry j+1, the top
@@ -163,7 +166,17 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                 return false;
             }
         }
-        const int32_t a_col = (la_col >= 0) ? c.col[la_col] : 0;
+        int32_t a_col = 0;
+        uint64_t a_nbw = 0;
+        if constexpr (ARCS) {
+            if (la_col >= 0) {
+                const ulonglong2 av = c.arcs[la_col];
+                a_col = (int32_t)av.x;
+                a_nbw = av.y;
+            }
+        } else {
+            a_col = (la_col >= 0) ? c.col[la_col] : 0;
+        }
         const uint64_t a_nb1 = (la_nb1 >= 0) ? c.nbr[la_nb1] : 0ull;
 
         // ---- fence: the previous round's stores and LDS writes are visible
@@ -178,6 +191,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                 const int r = __popcll(idle & below);
                 if (r < take) {
                     w = sh.rev[rev_n - 1 - r];
+                    nbw_ok = false;
                     mode = kArrive;
                     is_start = true;
                 }
@@ -189,6 +203,10 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         bool bad = false;
         if (mode == kDraw) {
             w = a_col;
+            if constexpr (ARCS) {
+                nbw = a_nbw;
+                nbw_ok = true;
+            }
             if (kh >= kMaxDraws) {
                 raise_err(c.err, kErrDrawOverflow, h);
                 bad = true;
@@ -216,7 +234,7 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         int64_t lb_st = -1, lb_nb = -1;
         if (arriving) {
             lb_st = w;
-            lb_nb = w;
+            lb_nb = (ARCS && nbw_ok) ? -1 : w;
         } else if (mode == kRetrace || mode == kRelease) {
             lb_st = x;
         } else if (mode == kPopLoad) {
@@ -244,6 +262,16 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
         }
 
         // ---- C. advance every walker by what its loads returned
+        if constexpr (ARCS) {
+            if (arriving) {
+                if (nbw_ok) {
+                    v_nb = nbw;
+                } else {
+                    nbw = v_nb;
+                    nbw_ok = true;
+                }
+            }
+        }
         bool claim = false, parked = false, push = false;
         int32_t wait_on = lane, pushed = -1;
         int rel_lo = 0, rel_hi = 0;     // stack entries to release this round
@@ -383,6 +411,8 @@ static __device__ bool wave_wilson_sample(const WaveSampleArgs &c, WaveShared &s
                         w = sh.cand_node[r];
                         v_st = sh.cand_st[r];
                         v_nb = sh.cand_nb[r];
+                        nbw = v_nb;
+                        nbw_ok = true;
                         mode = kArrive;
                         is_start = true;
                         claim = true;

@@ -129,6 +129,9 @@ __global__ __launch_bounds__(64) void wilson_lane_kernel(WilsonParams p) {
 }
 
 // ----------------------------------------------------------------- wave form
+// ARCS: draws read the arc record {target, target's adjacency record} of the
+// drawn column slot, so an arrival loads only the target's state word.
+template <bool ARCS>
 __global__ __launch_bounds__(64) void wilson_wave_kernel(WilsonParams p) {
     __shared__ WaveShared sh;
     const int lane = (int)threadIdx.x;
@@ -138,6 +141,7 @@ __global__ __launch_bounds__(64) void wilson_wave_kernel(WilsonParams p) {
     c.nnz = p.nnz;
     c.nbr = p.nbr;
     c.col = p.col;
+    c.arcs = p.arcs;
     c.root = p.root;
     c.k0 = p.k0;
     c.k1 = p.k1;
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(64) void wilson_wave_kernel(WilsonParams p) {
         c.keep_next = (keep_q >= 0 && p.next_out) ? p.next_out + (int64_t)keep_q * p.n : nullptr;
         c.keep_draws = (keep_q >= 0 && p.draws_out) ? p.draws_out + (int64_t)keep_q * p.n : nullptr;
         int64_t y1 = 0;
-        if (!wave_wilson_sample(c, sh, &y1, ws)) break;
+        if (!wave_wilson_sample<ARCS>(c, sh, &y1, ws)) break;
         if (lane == 0) {
             if (p.y1_per_sample) p.y1_per_sample[smp] = y1;
             ++ws.trees;
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(64) void wilson_wave_kernel(WilsonParams p) {
 // ------------------------------------------------------------ workgroup form
 // W wavefronts per sample (group_sample.h); one workgroup per slot.
 // (at least 4 waves per SIMD: 16 per CU, as in the wave form)
-template <int W>
+template <int W, bool ARCS>
 __global__ __launch_bounds__(kWave * W, 4) void wilson_group_kernel(WilsonParams p) {
     __shared__ GroupShared<W> sh;
     const int tid = (int)threadIdx.x;
@@ -182,6 +186,7 @@ __global__ __launch_bounds__(kWave * W, 4) void wilson_group_kernel(WilsonParams
     c.nnz = p.nnz;
     c.nbr = p.nbr;
     c.col = p.col;
+    c.arcs = p.arcs;
     c.root = p.root;
     c.k0 = p.k0;
     c.k1 = p.k1;
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(kWave * W, 4) void wilson_group_kernel(WilsonParams
         c.keep_next = (keep_q >= 0 && p.next_out) ? p.next_out + (int64_t)keep_q * p.n : nullptr;
         c.keep_draws = (keep_q >= 0 && p.draws_out) ? p.draws_out + (int64_t)keep_q * p.n : nullptr;
         int64_t y1 = 0;
-        if (!group_wilson_sample<W>(c, sh, &y1, ws)) break;
+        if (!group_wilson_sample<W, ARCS>(c, sh, &y1, ws)) break;
         if (tid == 0) {
             if (p.y1_per_sample) p.y1_per_sample[smp] = y1;
             ++ws.trees;
@@ -222,7 +227,10 @@ hipError_t launch_wilson_lane(const WilsonParams &p, int64_t slots, hipStream_t 
 }
 
 hipError_t launch_wilson_wave(const WilsonParams &p, int64_t slots, hipStream_t s) {
-    hipLaunchKernelGGL(wilson_wave_kernel, dim3((unsigned)slots), dim3(kWave), 0, s, p);
+    if (p.arcs)
+        hipLaunchKernelGGL(wilson_wave_kernel<true>, dim3((unsigned)slots), dim3(kWave), 0, s, p);
+    else
+        hipLaunchKernelGGL(wilson_wave_kernel<false>, dim3((unsigned)slots), dim3(kWave), 0, s, p);
     return hipGetLastError();
 }
 
@@ -230,21 +238,26 @@ hipError_t launch_wilson_wave(const WilsonParams &p, int64_t slots, hipStream_t 
 
 namespace lap {
 
-hipError_t launch_wilson_group(const WilsonParams &p, int64_t slots, int waves, hipStream_t s) {
+template <bool ARCS>
+static hipError_t launch_group_form(const WilsonParams &p, int64_t slots, int waves, hipStream_t s) {
     switch (waves) {
     case 2:
-        hipLaunchKernelGGL(wilson_group_kernel<2>, dim3((unsigned)slots), dim3(kWave * 2), 0, s, p);
+        hipLaunchKernelGGL((wilson_group_kernel<2, ARCS>), dim3((unsigned)slots), dim3(kWave * 2), 0, s, p);
         break;
     case 4:
-        hipLaunchKernelGGL(wilson_group_kernel<4>, dim3((unsigned)slots), dim3(kWave * 4), 0, s, p);
+        hipLaunchKernelGGL((wilson_group_kernel<4, ARCS>), dim3((unsigned)slots), dim3(kWave * 4), 0, s, p);
         break;
     case 8:
-        hipLaunchKernelGGL(wilson_group_kernel<8>, dim3((unsigned)slots), dim3(kWave * 8), 0, s, p);
+        hipLaunchKernelGGL((wilson_group_kernel<8, ARCS>), dim3((unsigned)slots), dim3(kWave * 8), 0, s, p);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_wilson_group(const WilsonParams &p, int64_t slots, int waves, hipStream_t s) {
+    return p.arcs ? launch_group_form<true>(p, slots, waves, s) : launch_group_form<false>(p, slots, waves, s);
 }
 
 }  // namespace lap
