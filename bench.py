@@ -1,20 +1,32 @@
-"""Benchmark of the hot path: one step = Wilson loop-erased-walk sampling
+"""Benchmark of the hot path.  One step = Wilson loop-erased-walk sampling
 (omega trees rooted at the max-degree node), omega uniform-start and omega
 stationary-start absorbed walks, and the FP64 assembly of diag(L^dagger),
-closeness and Kemeny's constant, on a Barabasi-Albert graph n = 100,000,
-m = 5 with omega = 4096 (synthetic input, resident in HBM before timing).
+closeness and Kemeny's constant (Alg. 2 + Alg. 4), with inputs resident in
+HBM before timing.
 
-Prints one JSON line.  `value` is walk steps per second (Wilson draws plus
-absorbed-walk draws) of the whole job.
+Headline: R-MAT scale 22 (edge factor 16, a/b/c/d = .57/.19/.19/.05),
+symmetrised, self-loops and duplicates dropped, largest component kept
+(n = 2.39 M, 2m = 128.3 M), omega = 512 -- the largest single-GPU workload.
+`value` is walk steps per second (Wilson draws plus absorbed-walk draws).
+
+Sub-records: the small ER(256, 0.05) workload (omega = 2^14, with its accuracy
+against the dense pseudo-inverse), the mid Barabasi-Albert workload (n = 10^5,
+m = 5, omega = 4096), the random-gather sweep, the 512-graph batch, serving on
+a resident R-MAT 21 graph, SpanTree, loop-included paths, node pairs, the
+landmark study and Kemeny's constant of synthetic families.  Each workload
+with a CPU figure times the oracle on the host's cores on a bounded sample.
+
+Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
-
-import numpy as np
 import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -22,17 +34,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WILSON_BYTES_PER_STEP = 33.0     # offsets 16 + column 4 + draw count 8 + next 4 + tree flag 1
 RETRACE_BYTES_PER_NODE = 5.0
-LOADS_PER_WILSON_STEP = 3        # dependent random loads per draw: column, target state, target offsets
-CHASE_BYTES_PER_LOAD = 128       # FETCH_SIZE per 4 GiB pointer-chase load, measured on the gather benchmark
+SEED = 1
 
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wilson_wave_traffic.json")
+# everything the Wilson kernels and their launch configuration are built from:
+# a counter summary taken on other sources is not used
 KERNEL_SOURCES = ["paper_2311_10290_amd/csrc/" + f for f in
-                  ("wave_sample.h", "wilson.hip", "lap_device.h")]
+                  ("wilson.hip", "wave_sample.h", "group_sample.h", "lap_device.h", "lap_params.h",
+                   "lap_launch.h", "lap_host.h", "capi.cpp")]
+TRAFFIC = {
+    "large": dict(file="profiles/traffic_wilson_group_rmat22.json", kernel="wilson_group_kernel<8, true>",
+                  workload="R-MAT scale 22 LCC, omega=512, one launch"),
+    "mid": dict(file="profiles/traffic_wilson_wave_ba100k.json", kernel="wilson_wave_kernel<false>",
+                workload="Barabasi-Albert n=100000 m=5, omega=4096, one launch"),
+}
+SECTIONS = ("large", "small", "mid", "gather", "spantree", "loop_paths", "pairs", "landmark", "kc_families",
+            "batched", "serving")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash():
-    import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -40,100 +63,299 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(part="bytes_per_launch"):
-    """HBM bytes per Wilson launch (or its FETCH_SIZE part) from the committed
-    counter summary, if it was taken on the current kernel sources; otherwise
-    null."""
+def measured_traffic(which):
+    """The committed counter summary of one Wilson launch of the workload, if
+    it was taken on the current kernel sources; otherwise None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, TRAFFIC[which]["file"])) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
-        return None
-    return t["bytes_per_launch"] if part == "bytes_per_launch" else t["FETCH_SIZE"]["bytes"]
+    return t if t.get("kernel_hash") == kernel_hash() else None
 
 
-def write_traffic(pmc_dir):
-    """Reduce the counter runs under pmc_dir to the traffic summary for the
-    current kernel sources.  Expects the databases of four one-counter runs:
-    copy_FETCH_SIZE/ and copy_WRITE_SIZE/ (``--copy-calibration``: a 1 GiB
-    device copy), pmc_FETCH_SIZE/ and pmc_WRITE_SIZE/ (one plain step).  Each
-    counter is scaled by copy bytes / what it read for the copy."""
+def _csv_counters(path, kernel):
+    """Per-dispatch counter values {counter: [v per dispatch]} of the dispatches
+    whose kernel name contains `kernel`, from rocprofv3 CSV output under path."""
+    import csv
     import glob
-    import sqlite3
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit(f"expected one counter_collection.csv under {path}, found {files}")
+    per = {}
+    with open(files[0]) as fh:
+        for r in csv.DictReader(fh):
+            if kernel in r["Kernel_Name"]:
+                per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    return [per[k] for k in sorted(per)]
 
-    def per_dispatch(sub, counter, kernel):
-        db, = glob.glob(os.path.join(pmc_dir, sub, "*_results.db"))
-        con = sqlite3.connect(db)
-        rows = con.execute("select dispatch_id, sum(value) from counters_collection where counter_name=? and "
-                           "kernel_name like ? group by dispatch_id order by dispatch_id",
-                           (counter, f"%{kernel}%")).fetchall()
-        con.close()
-        return [r[1] for r in rows]
 
-    copy_kib = 1 << 20
-    res = {"kernel": "wilson_wave_kernel", "workload": "Barabasi-Albert n=100000 m=5, omega=4096, one launch",
-           "kernel_hash": kernel_hash()}
-    total = 0.0
-    for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        cal = copy_kib / per_dispatch(f"copy_{c}", c, "copyBuffer")[0]
-        raw = per_dispatch(f"pmc_{c}", c, "wilson_wave")
-        res[c] = {"raw_kib_per_dispatch": raw, "calibration": cal, "bytes": raw[0] * 1024 * cal}
-        total += raw[0] * 1024 * cal
-    res["bytes_per_launch"] = total
-    with open(TRAFFIC_FILE, "w") as fh:
+def write_traffic(pmc_dir, which):
+    """Reduce the counter runs under pmc_dir to the traffic summary of one
+    Wilson launch of the workload.  Expects four runs (rocprofv3 CSV output):
+    copy_fetch/ and copy_write/ (``--copy-calibration``: a 1 GiB device copy)
+    and <which>_fetch/, <which>_write/ (``--only <which> --steps 1 --warmup 0``),
+    fetch runs with TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum, write
+    runs with TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum (the inputs of FETCH_SIZE
+    and WRITE_SIZE), plus <which>_fetch/bench.json (the run's JSON line, for
+    the draws per launch).  Each byte count is scaled by the copy's bytes over
+    what the same counters read for the copy."""
+    def fetch_bytes(c):
+        rd, r32, bub = c["TCC_EA0_RDREQ_sum"], c["TCC_EA0_RDREQ_32B_sum"], c["TCC_BUBBLE_sum"]
+        return bub * 128 + (rd - bub - r32) * 64 + r32 * 32
+
+    def write_bytes(c):
+        wr, w64 = c["TCC_EA0_WRREQ_sum"], c["TCC_EA0_WRREQ_64B_sum"]
+        return (wr - w64) * 32 + w64 * 64
+
+    spec = TRAFFIC[which]
+    copy_bytes = 1 << 30
+    cal_f = copy_bytes / fetch_bytes(_csv_counters(os.path.join(pmc_dir, "copy_fetch"), "copyBuffer")[0])
+    cal_w = copy_bytes / write_bytes(_csv_counters(os.path.join(pmc_dir, "copy_write"), "copyBuffer")[0])
+    f = _csv_counters(os.path.join(pmc_dir, f"{which}_fetch"), spec["kernel"])
+    w = _csv_counters(os.path.join(pmc_dir, f"{which}_write"), spec["kernel"])
+    if len(f) != 1 or len(w) != 1:
+        raise SystemExit(f"expected one {spec['kernel']} dispatch per run, got {len(f)} and {len(w)}")
+    with open(os.path.join(pmc_dir, f"{which}_fetch", "bench.json")) as fh:
+        b = json.loads(fh.read().strip().splitlines()[-1])
+    draws = b["wilson_steps_per_step"] if which == "large" else b["mid"]["wilson_steps_per_step"]
+    res = {"kernel": spec["kernel"], "workload": spec["workload"], "kernel_hash": kernel_hash(),
+           "draws_per_launch": draws,
+           "fetch": {"counters": f[0], "raw_bytes": fetch_bytes(f[0]), "calibration": cal_f,
+                     "bytes": fetch_bytes(f[0]) * cal_f},
+           "write": {"counters": w[0], "raw_bytes": write_bytes(w[0]), "calibration": cal_w,
+                     "bytes": write_bytes(w[0]) * cal_w},
+           "read_requests_per_launch": f[0]["TCC_EA0_RDREQ_sum"]}
+    res["bytes_per_launch"] = res["fetch"]["bytes"] + res["write"]["bytes"]
+    res["bytes_per_draw"] = res["bytes_per_launch"] / draws
+    res["read_requests_per_draw"] = res["read_requests_per_launch"] / draws
+    with open(os.path.join(ROOT, spec["file"]), "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res))
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def cpu_baseline(og, root, omega_full, seed, budget_s=15.0):
-    """The oracle (C, OpenMP over samples) on a bounded sample of the same workload."""
-    from oracle import native
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t = time.perf_counter()
-    w = native.wilson(og, root, omega_full, seed, n_samples=64, want_y1=True, threads=threads)
-    dt = time.perf_counter() - t
-    n_s = int(min(omega_full, max(64, 64 * budget_s / max(dt, 1e-3))))
-    # when the whole workload is shorter than the budget, it is repeated
-    reps, steps, t = 0, 0, time.perf_counter()
-    while True:
-        w = native.wilson(og, root, omega_full, seed, n_samples=n_s, threads=threads)
-        a1 = native.absorbed(og, root, n_s, seed, 1, omega_total=omega_full, threads=threads)
-        a2 = native.absorbed(og, root, n_s, seed, 2, omega_total=omega_full, want_y2=False, threads=threads)
-        steps += int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
-        reps += 1
-        dt = time.perf_counter() - t
-        if n_s < omega_full or dt >= 0.7 * budget_s:
-            break
-    # one thread on a smaller sample: the per-core rate
-    n1 = max(8, n_s // (2 * threads))
-    t1 = time.perf_counter()
-    w = native.wilson(og, root, omega_full, seed, n_samples=n1, threads=1)
-    a1 = native.absorbed(og, root, n1, seed, 1, omega_total=omega_full, threads=1)
-    a2 = native.absorbed(og, root, n1, seed, 2, omega_total=omega_full, want_y2=False, threads=1)
-    steps1 = int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
-    dt1 = time.perf_counter() - t1
+def host_cpu():
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
+    return model
+
+
+def oracle_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(og, root, omega_full, budget_s=15.0, probe=64):
+    """The oracle (C, OpenMP over samples) on a bounded sample of the same
+    workload: the first n_s samples (Wilson + both absorbed-walk kinds), n_s
+    sized from a probe run to take about budget_s; repeated when the whole
+    workload is shorter than that.  Then one thread on a smaller sample."""
+    from oracle import native
+    threads = oracle_threads()
+    probe = min(probe, omega_full)
+    t = time.perf_counter()
+    native.wilson(og, root, omega_full, SEED, n_samples=probe, want_y1=True, threads=threads)
+    dt = time.perf_counter() - t
+    n_s = int(min(omega_full, max(probe, probe * budget_s / max(dt, 1e-3))))
+    reps, steps, trees, t = 0, 0, 0, time.perf_counter()
+    while True:
+        w = native.wilson(og, root, omega_full, SEED, n_samples=n_s, threads=threads)
+        a1 = native.absorbed(og, root, n_s, SEED, 1, omega_total=omega_full, threads=threads)
+        a2 = native.absorbed(og, root, n_s, SEED, 2, omega_total=omega_full, want_y2=False, threads=threads)
+        steps += int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
+        trees += n_s
+        reps += 1
+        dt = time.perf_counter() - t
+        if n_s < omega_full or dt >= 0.7 * budget_s:
+            break
+    n1 = max(2, min(n_s, n_s // (2 * threads)))
+    t1 = time.perf_counter()
+    w = native.wilson(og, root, omega_full, SEED, n_samples=n1, threads=1)
+    a1 = native.absorbed(og, root, n1, SEED, 1, omega_total=omega_full, threads=1)
+    a2 = native.absorbed(og, root, n1, SEED, 2, omega_total=omega_full, want_y2=False, threads=1)
+    steps1 = int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
+    dt1 = time.perf_counter() - t1
     return {"value": steps / dt, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_s} of {omega_full} samples (Wilson + both absorbed-walk kinds), "
                       f"{reps} pass(es), {dt:.1f} s",
-            "trees_per_s": reps * n_s / dt,
+            "trees_per_s": trees / dt,
             "single_thread": {"value": steps1 / dt1, "unit": "walk steps/s",
                               "sample": f"first {n1} samples, {dt1:.1f} s"},
-            "host_cpu": model, "host_cpus": os.cpu_count()}
+            "host_cpu": host_cpu(), "host_cpus": os.cpu_count()}
 
 
-def bench_batch(lap, gg, n_jobs):
+def _out_tensors(n):
+    import torch
+    dev = torch.device("cuda:0")
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("diag", "diag_se", "closeness")}
+    out.update({k: torch.empty(1, dtype=torch.float64, device=dev) for k in ("trace", "kemeny", "kemeny_se")})
+    return out
+
+
+def timed_steps(lap, g, omega, root, steps, warmup, B=64):
+    """Run warmup + steps plain steps on torch's current stream; time the
+    steps between two device synchronisations, with per-kernel HIP-event
+    timing (on the streams the kernels run on) over the timed region."""
+    import torch
+    out = _out_tensors(g.n)
+    stream = torch.cuda.current_stream()
+    for i in range(warmup):
+        g.estimate(omega, SEED, root, B=B, out=out, stream=stream)
+    torch.cuda.synchronize()
+    lap.prof_reset()
+    lap.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        g.estimate(omega, SEED, root, B=B, out=out, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lap.prof_enable(False)
+    st = g.last_stats()
+    kern = {}
+    for name in ("wilson_group", "wilson_wave", "wilson_lane", "absorbed", "assemble"):
+        ms, n = lap.prof_read(name)
+        if n:
+            kern[name] = {"ms_avg": ms / n, "launches": n}
+    wk = next(k for k in ("wilson_group", "wilson_wave", "wilson_lane") if k in kern)
+    return dt, st, kern, wk, out
+
+
+def roofline(st, n, kern_ms, traffic, kernel):
+    alg = WILSON_BYTES_PER_STEP * st["wilson_steps"] + RETRACE_BYTES_PER_NODE * n * st["trees"]
+    achieved = alg / (kern_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "kernel": kernel, "bytes_per_launch": alg, "kernel_ms": kern_ms}
+
+
+def request_rate(traffic, kern_ms, gather):
+    """Read requests per second that reach memory (L2 misses, counted) against
+    the measured random-request peak at the 4 GiB tier."""
+    if not traffic:
+        return None
+    rps = traffic["read_requests_per_launch"] / (kern_ms * 1e-3)
+    out = {"read_requests_per_draw": traffic["read_requests_per_draw"], "read_requests_per_s": rps,
+           "bytes_per_draw": traffic["bytes_per_draw"]}
+    if gather:
+        peak = gather["tiers"]["4GiB"]["peak"]
+        out["frac_of_random_request_peak_4GiB"] = rps / peak
+    return out
+
+
+# ----------------------------------------------------------------- workloads
+def rmat_graph(lap, gg, scale):
+    t = time.perf_counter()
+    src, dst = gg.rmat(scale, 16, seed=0)
+    g = lap.Graph(1 << scale, src, dst, keep_lcc=True)
+    log(f"R-MAT {scale} LCC n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
+    return g, src, dst
+
+
+def bench_small(lap, gg, with_cpu, gather):
+    """Small workload: ER(256, 0.05), graph seed 0, resampled until connected,
+    root = max degree, omega = 2^14; accuracy against the dense FP64
+    pseudo-inverse at Philox seed 1 (CPU leg), GPU and CPU rates."""
+    n, omega = 256, 1 << 14
+    src, dst, _ = gg.erdos_renyi_connected(n, 0.05, 0)
+    g = lap.Graph(n, src, dst)
+    root = g.max_deg_node
+    reps = 20
+    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, reps, 2)
+    kms = kern[wk]["ms_avg"]
+    res = {"workload": "ER(256, 0.05) seed 0 connected, root = max degree, omega = 2^14, Philox seed 1",
+           "s_per_step": dt / reps, "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) * reps / dt,
+           "trees_per_s": omega * reps / dt, "wilson_kernel": wk, "wilson_kernel_ms": kms,
+           "kernel_ms": {k: v["ms_avg"] for k, v in kern.items()},
+           "wilson_steps_per_step": st["wilson_steps"],
+           "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
+    # the walk state of 4096 slots x 256 nodes (8 MB) sits in the caches: the
+    # reference is the L2-tier random-request rate of the sweep
+    if gather:
+        loads = 3.0 * st["wilson_steps"] / (kms * 1e-3)
+        res["cache_tier"] = {"state_bytes": 8 * n * min(omega, 4096), "loads_per_draw_assumed": 3,
+                             "loads_per_s": loads, "peak_4MiB": gather["tiers"]["4MiB"]["peak"],
+                             "frac_of_4MiB_peak": loads / gather["tiers"]["4MiB"]["peak"]}
+    if with_cpu:
+        from oracle import csr as ocsr, dense, native
+        og = ocsr.build_csr(n, src, dst)
+        L = dense.laplacian(og)
+        t = time.perf_counter()
+        Ld = dense.pinv_eigh(L)
+        t_eigh = time.perf_counter() - t
+        t = time.perf_counter()
+        Ld2 = dense.pinv_inverse(L)
+        t_inv = time.perf_counter() - t
+        c_true = dense.closeness(Ld)
+        k_true = dense.kemeny_spectral(og)
+        c_gpu = out["closeness"].cpu().numpy()
+        k_gpu = float(out["kemeny"].item())
+        rel_c = np.abs(c_gpu - c_true) / c_true
+        res["accuracy_vs_dense_pinv"] = {
+            "kemeny_rel_err": abs(k_gpu - k_true) / k_true, "kemeny_exact": k_true,
+            "kemeny_z": (k_gpu - k_true) / float(out["kemeny_se"].item()),
+            "closeness_mean_rel_err": float(rel_c.mean()), "closeness_max_rel_err": float(rel_c.max()),
+            "target": "<= 1e-2 relative (kappa and mean closeness)",
+            "routes_agree": float(np.abs(Ld - Ld2).max())}
+        # the SpanTree estimators (Alg. 1, Alg. 3) on the same 2^14 Wilson trees
+        sp = g.spantree_estimate(omega, SEED, root, B=64)
+        rel_cs = np.abs(sp["closeness"] - c_true) / c_true
+        res["accuracy_vs_dense_pinv"]["spantree_same_trees"] = {
+            "kemeny_rel_err": abs(float(sp["kemeny"][0]) - k_true) / k_true,
+            "kemeny_z": (float(sp["kemeny"][0]) - k_true) / float(sp["kemeny_se"][0]),
+            "closeness_mean_rel_err": float(rel_cs.mean()), "closeness_max_rel_err": float(rel_cs.max())}
+        res["cpu_baseline"] = cpu_baseline(og, root, omega, budget_s=5.0)
+        res["cpu_baseline"]["dense_pinv_s"] = {"eigh": t_eigh, "inverse": t_inv}
+    g.close()
+    return res
+
+
+def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
+    """Mid workload: Barabasi-Albert n = 100,000, m = 5, graph seed 0, root =
+    max degree, omega = 4096 (wave form)."""
+    n, m, omega = 100_000, 5, 4096
+    src, dst = gg.barabasi_albert(n, m, 0)
+    g = lap.Graph(n, src, dst)
+    root = g.max_deg_node
+    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, steps, warmup)
+    kms = kern[wk]["ms_avg"]
+    traffic = measured_traffic("mid")
+    res = {"workload": "Barabasi-Albert n=100000 m=5, root = max degree, omega = 4096",
+           "n": g.n, "nnz": g.nnz, "omega": omega, "s_per_step": dt / steps,
+           "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) * steps / dt,
+           "trees_per_s": omega * steps / dt, "wilson_steps_per_step": st["wilson_steps"],
+           "absorbed_steps_per_step": st["absorbed_steps"],
+           "kernel_ms": {k: v["ms_avg"] for k, v in kern.items()},
+           "roofline": roofline(st, g.n, kms, traffic, TRAFFIC["mid"]["kernel"]),
+           "requests": request_rate(traffic, kms, gather),
+           "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
+    if with_cpu:
+        from oracle import csr as ocsr
+        res["cpu_baseline"] = cpu_baseline(ocsr.build_csr(n, src, dst), root, omega, budget_s=10.0)
+    return res, g, root
+
+
+def bench_gather(lap):
+    """Random 8-byte gather rates at three working sets: the pointer chase over
+    lanes 2^14..2^22, independent loads over lanes {2^14, 2^16, 2^18, 2^20} x
+    loads in flight {1, 2, 4, 8, 16}; the peak of each tier is the maximum."""
+    tiers = {}
+    for label, nbytes in (("4MiB", 4 << 20), ("128MiB", 128 << 20), ("4GiB", 4 << 30)):
+        chase = {str(1 << lg): lap.bench_gather(nbytes, 1 << lg, 1) for lg in range(14, 23)}
+        indep = {f"{1 << lg}x{d}": lap.bench_gather(nbytes, 1 << lg, 0, d) for lg in (14, 16, 18, 20)
+                 for d in (1, 2, 4, 8, 16)}
+        tiers[label] = {"chase": chase, "independent": indep,
+                        "chase_peak": max(chase.values()), "independent_peak": max(indep.values()),
+                        "peak": max(max(chase.values()), max(indep.values()))}
+        log(f"gather {label}: chase peak {tiers[label]['chase_peak'] / 1e9:.1f} G/s, "
+            f"independent peak {tiers[label]['independent_peak'] / 1e9:.1f} G/s")
+    return {"unit": "random 8-byte loads/s (one memory request each at the 4 GiB tier)", "tiers": tiers}
+
+
+def bench_batch(lap, gg, n_jobs, with_cpu):
     """Many-graph batch: 512 jobs (half ER with average degree in [8, 20],
     half BA with m in 2..8, n log-uniform in [1000, 200000], omega uniform in
     [256, 4096], job list seed 2), each estimating closeness and Kemeny's
@@ -147,8 +369,6 @@ def bench_batch(lap, gg, n_jobs):
         s, d = gg.job_edges(sp)
         jobs.append(dict(n=sp["n"], src=s, dst=d, keep_lcc=True, root=-1, omega=sp["omega"], seed=1))
     log(f"batch: generated {n_jobs} graphs in {time.perf_counter() - t0:.1f} s")
-    # autotune on the whole batch (a probe subset of the jobs favours smaller
-    # pools than the whole batch runs best with), then time the tuned batch
     b = lap.Batch(jobs)
     t_tune = time.perf_counter()
     tuning, tune_ms = b.autotune()
@@ -164,13 +384,10 @@ def bench_batch(lap, gg, n_jobs):
     bt = (time.perf_counter() - t) / reps
     st = b.stats()
     steps = st["wilson_steps"] + st["absorbed_steps"]
-    # plain path, one job after another (graph preparation untimed)
     plain_s = 0.0
-    dev = torch.device("cuda:0")
     for j, job in enumerate(jobs):
         g = lap.Graph(job["n"], job["src"], job["dst"], keep_lcc=True)
-        out = {k: torch.empty(g.n, dtype=torch.float64, device=dev) for k in ("diag", "closeness")}
-        out.update({k: torch.empty(1, dtype=torch.float64, device=dev) for k in ("trace", "kemeny", "kemeny_se")})
+        out = _out_tensors(g.n)
         g.estimate(job["omega"], 1, -1, B=1, se=False, out=out)         # warm the workspace
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -180,18 +397,41 @@ def bench_batch(lap, gg, n_jobs):
         g.close()
         if (j + 1) % 128 == 0:
             log(f"batch: plain path {j + 1}/{len(jobs)}")
-    return {"workload": f"{n_jobs} graphs (ER/BA mix, n log-uniform 1e3..2e5, omega 256..4096), one launch",
-            "jobs": n_jobs, "total_nodes": int(sum(i["n"] for i in b.info)),
-            "total_trees": st["trees"], "walk_steps": steps,
-            "batched_s": bt, "batched_steps_per_s": steps / bt, "batched_trees_per_s": st["trees"] / bt,
-            "plain_s": plain_s, "plain_steps_per_s": steps / plain_s, "plain_trees_per_s": st["trees"] / plain_s,
-            "speedup_batched_vs_plain": plain_s / bt,
-            "tuning": {"pool": tuning.pool, "chunk_nodes": tuning.chunk_nodes, "use_graph": tuning.use_graph}}
+    res = {"workload": f"{n_jobs} graphs (ER/BA mix, n log-uniform 1e3..2e5, omega 256..4096), one launch",
+           "jobs": n_jobs, "total_nodes": int(sum(i["n"] for i in b.info)),
+           "total_trees": st["trees"], "walk_steps": steps,
+           "batched_s": bt, "batched_steps_per_s": steps / bt, "batched_trees_per_s": st["trees"] / bt,
+           "plain_s": plain_s, "plain_steps_per_s": steps / plain_s, "plain_trees_per_s": st["trees"] / plain_s,
+           "speedup_batched_vs_plain": plain_s / bt,
+           "tuning": {"pool": tuning.pool, "chunk_nodes": tuning.chunk_nodes, "use_graph": tuning.use_graph,
+                      "tuned_ms": tune_ms}}
+    if with_cpu:
+        # the oracle on every 32nd job (16 jobs, whole sample budgets)
+        from oracle import csr as ocsr, native
+        threads = oracle_threads()
+        steps_c, trees_c, dt = 0, 0, 0.0
+        for j in range(0, n_jobs, 32):
+            job = jobs[j]
+            og = ocsr.build_csr(job["n"], job["src"], job["dst"], keep_lcc=True)
+            root = ocsr.landmark(og)
+            tt = time.perf_counter()
+            w = native.wilson(og, root, job["omega"], 1, threads=threads)
+            a1 = native.absorbed(og, root, job["omega"], 1, 1, threads=threads)
+            a2 = native.absorbed(og, root, job["omega"], 1, 2, want_y2=False, threads=threads)
+            dt += time.perf_counter() - tt      # graph preparation untimed
+            steps_c += int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
+            trees_c += job["omega"]
+        res["cpu_baseline"] = {"value": steps_c / dt, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
+                               "sample": f"every 32nd job ({len(range(0, n_jobs, 32))} jobs, whole budgets), "
+                                         f"{dt:.1f} s", "trees_per_s": trees_c / dt,
+                               "est_total_s": steps / (steps_c / dt), "host_cpu": host_cpu()}
+    b.close()
+    return res
 
 
 def _replay(lap, srv, qs, qid0):
     """Submit each query at its arrival time (seconds from start), drive the
-    loop, return per-query latencies (completion - submission)."""
+    loop, return per-query results with latency (completion - submission)."""
     kinds = {0: lap.Server.CLOSENESS, 1: lap.Server.RESISTANCE, 2: lap.Server.KEMENY}
     t0 = time.perf_counter()
     i, out = 0, []
@@ -206,9 +446,113 @@ def _replay(lap, srv, qs, qid0):
         if i < len(qs) and not srv.pending()["inflight"]:
             time.sleep(min(0.001, max(0.0, qs[i]["t"] - (time.perf_counter() - t0))))
     wall = time.perf_counter() - t0
+    return out, wall
+
+
+def _latency_summary(out):
     lat = np.array([r["t_done"] - r["t_submit"] for r in out])
-    bad = sum(r["status"] != 0 for r in out)
-    return lat, wall, bad
+    res = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "errors": int(sum(r["status"] != 0 for r in out)), "by_kind": {}}
+    for k, name in ((0, "closeness"), (1, "resistance"), (2, "kemeny")):
+        lk = np.array([r["t_done"] - r["t_submit"] for r in out if r["kind"] == k])
+        if len(lk):
+            res["by_kind"][name] = {"queries": len(lk), "p50_ms": float(np.percentile(lk, 50) * 1e3),
+                                    "p99_ms": float(np.percentile(lk, 99) * 1e3)}
+    return res
+
+
+def _serial(lap, srv, qs, qid0):
+    """The same queries one at a time: each is submitted when the previous
+    one has completed (no batching across queries).  Returns the wall time."""
+    kinds = {0: lap.Server.CLOSENESS, 1: lap.Server.RESISTANCE, 2: lap.Server.KEMENY}
+    t0 = time.perf_counter()
+    bad = 0
+    for q in qs:
+        srv.submit(qid0 + q["qid"], kinds[q["kind"]], q["budget"], q["u"], q["w"])
+        done = []
+        while not done:
+            srv.step(wait=True)
+            done = srv.poll()
+        bad += sum(r["status"] != 0 for r in done)
+    return time.perf_counter() - t0, bad
+
+
+def bench_serve(lap, gg, n_queries, with_cpu, repeats=3):
+    """Serving: resident R-MAT scale-21 graph (edge factor 16, a/b/c/d =
+    .57/.19/.19/.05, symmetrised, self-loops and duplicates dropped, largest
+    component); Poisson arrivals mixing single-node closeness (64..1024 walks,
+    log-uniform), pairwise resistance (1024 walk pairs) and Kemeny (256
+    samples) in proportions 45/45/10.  Saturation throughput is measured with
+    every query submitted at once; latency percentiles (overall and per query
+    kind) at 50% and 80% of it, the 80% run repeated on the same server."""
+    g, src, dst = rmat_graph(lap, gg, 21)
+    if not with_cpu:
+        del src, dst
+    srv = lap.Server(g, seed=1, global_samples=256)
+    qs = gg.query_stream(g.n, n_queries, qps=1.0, seed=3)
+    for q in qs:
+        q["t"] = 0.0
+    out_sat, wall = _replay(lap, srv, qs, 0)
+    sat = n_queries / wall
+    log(f"serve: saturation {sat:.1f} queries/s")
+    n_serial = min(n_queries, 100)
+    wall_serial, bad_serial = _serial(lap, srv, qs[:n_serial], 10_000_000)
+    log(f"serve: one query at a time {n_serial / wall_serial:.1f} queries/s")
+    res = {"workload": "R-MAT scale 21 LCC resident; Poisson mix 45% closeness (64-1024 walks), "
+                       "45% resistance (1024 walk pairs), 10% Kemeny (256 samples)",
+           "n": g.n, "nnz": g.nnz, "queries": n_queries, "saturation_qps": sat,
+           "closed_loop": _latency_summary(out_sat),
+           "errors": int(sum(r["status"] != 0 for r in out_sat)) + int(bad_serial),
+           "one_at_a_time_qps": n_serial / wall_serial,
+           "speedup_served_vs_one_at_a_time": sat / (n_serial / wall_serial), "runs": []}
+    loads = [0.5] + [0.8] * repeats
+    for k, frac in enumerate(loads):
+        qs = gg.query_stream(g.n, n_queries, qps=frac * sat, seed=4 + min(k, 1))
+        out, wall = _replay(lap, srv, qs, (k + 1) * 1_000_000)
+        r = {"offered_qps": frac * sat, "load": frac, "achieved_qps": n_queries / wall}
+        r.update(_latency_summary(out))
+        res["runs"].append(r)
+        log(f"serve: {frac:.0%} load p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms")
+    p99s = [r["p99_ms"] for r in res["runs"] if r["load"] == 0.8]
+    res["p99_80pct_spread"] = (max(p99s) - min(p99s)) / min(p99s)
+    srv.close()
+    if with_cpu:
+        res["cpu_baseline"] = serve_cpu(gg, g, src, dst)
+    g.close()
+    return res
+
+
+def serve_cpu(gg, g, src, dst, budget_s=12.0):
+    """The oracle answering the query stream's first queries one after another
+    (closeness and resistance walks on one thread, Kemeny samples on all
+    cores), as a reference for the served latencies."""
+    from oracle import csr as ocsr, native
+    og = ocsr.build_csr(1 << 21, src, dst, keep_lcc=True)
+    root = ocsr.landmark(og)
+    threads = oracle_threads()
+    qs = gg.query_stream(og.n, 200, qps=1.0, seed=3)
+    lat = {0: [], 1: [], 2: []}
+    t_all = time.perf_counter()
+    for q in qs:
+        t = time.perf_counter()
+        if q["kind"] == 0:
+            native.query_walks(og, root, 1, q["qid"], q["u"], 0, q["u"], q["u"], q["budget"])
+        elif q["kind"] == 1:
+            native.query_walks(og, root, 1, q["qid"], q["u"], 0, q["u"], q["w"], q["budget"])
+            native.query_walks(og, root, 1, q["qid"], q["w"], 1, q["w"], q["u"], q["budget"])
+        else:
+            native.wilson(og, root, q["budget"], 1, qid=q["qid"], threads=threads)
+            native.absorbed(og, root, q["budget"], 1, 2, qid=q["qid"], want_y2=False, threads=threads)
+        lat[q["kind"]].append(time.perf_counter() - t)
+        if time.perf_counter() - t_all > budget_s:
+            break
+    done = sum(len(v) for v in lat.values())
+    wall = time.perf_counter() - t_all
+    return {"kind": "oracle", "cores": threads, "queries": done, "qps": done / wall,
+            "sample": f"first {done} queries of the stream, one after another, {wall:.1f} s",
+            "mean_ms_by_kind": {name: float(np.mean(lat[k]) * 1e3) for k, name in
+                                ((0, "closeness"), (1, "resistance"), (2, "kemeny")) if lat[k]},
+            "host_cpu": host_cpu()}
 
 
 def bench_spantree(lap, g, root, omega):
@@ -290,7 +634,6 @@ def bench_pairs(lap, g, root, n, omega=1024, n_pairs=256):
     ok = r["r"] > 0
     out["median_rel_se_r"] = float(np.median(r["r_se"][ok] / r["r"][ok]))
     out["mean_path_len"] = out["check0"]["path_steps"] / out["paths"]
-    # whole rows of L_v^{-1} for 64 of the sources, same samples
     src = s[:64]
     g.lv_rows(src, omega, 1, root, check=0)
     lap.prof_reset()
@@ -330,12 +673,13 @@ def bench_landmark(lap, gg):
     return res
 
 
-def bench_kc_families(lap, gg, n):
+def bench_kc_families(lap, gg, n, er_omega):
     """Kemeny's constant of synthetic families (the paper's Sec. 6 study on
     BA, ER and hyperbolic graphs): BA with m = 2..6; ER with average degree
     200..1000 (p = 2..10 x 1e-4 at 1e6 nodes); hyperbolic with gamma =
     2.2..3.0 and average degree 10 (largest component); 256 samples each,
-    all 15 graphs in one batched launch."""
+    er_omega for the ER graphs (their stationary-start walk lengths vary
+    most), all 15 graphs in one batched launch."""
     import torch
     t0 = time.perf_counter()
     jobs, labels = [], []
@@ -345,7 +689,7 @@ def bench_kc_families(lap, gg, n):
         labels.append(f"BA m={m}")
     for k in (200, 400, 600, 800, 1000):
         s, d = gg.erdos_renyi(n, k / (n - 1), 200 + k)
-        jobs.append(dict(n=n, src=s, dst=d, keep_lcc=True, root=-1, omega=256, seed=1))
+        jobs.append(dict(n=n, src=s, dst=d, keep_lcc=True, root=-1, omega=er_omega, seed=1))
         labels.append(f"ER avg degree {k}")
     for gamma in (2.2, 2.4, 2.6, 2.8, 3.0):
         s, d = gg.hyperbolic(n, 10.0, gamma, 300 + int(round(gamma * 10)))
@@ -368,113 +712,15 @@ def bench_kc_families(lap, gg, n):
     rows = []
     for j, lab in enumerate(labels):
         r = b.result(j)
-        rows.append({"graph": lab, "n_lcc": int(b.info[j]["n"]), "kemeny": float(r["kemeny"][0]),
-                     "kemeny_se": float(r["kemeny_se"][0]),
-                     "kemeny_over_n": float(r["kemeny"][0]) / b.info[j]["n"]})
+        rows.append({"graph": lab, "n_lcc": int(b.info[j]["n"]), "omega": int(b.info[j]["omega"]),
+                     "kemeny": float(r["kemeny"][0]), "kemeny_se": float(r["kemeny_se"][0]),
+                     "kemeny_over_n": float(r["kemeny"][0]) / b.info[j]["n"],
+                     "rel_se": float(r["kemeny_se"][0] / r["kemeny"][0])})
     st = b.stats()
     b.close()
-    return {"workload": f"15 synthetic graphs, n={n}, 256 samples each, one batched launch", "s": dt,
-            "prepare_s": gen_s, "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) / dt,
+    return {"workload": f"15 synthetic graphs, n={n}, 256 samples each ({er_omega} for ER), one batched launch",
+            "s": dt, "prepare_s": gen_s, "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) / dt,
             "graphs": rows}
-
-
-def _serial(lap, srv, qs, qid0):
-    """The same queries one at a time: each is submitted when the previous
-    one has completed (no batching across queries).  Returns the wall time."""
-    kinds = {0: lap.Server.CLOSENESS, 1: lap.Server.RESISTANCE, 2: lap.Server.KEMENY}
-    t0 = time.perf_counter()
-    bad = 0
-    for q in qs:
-        srv.submit(qid0 + q["qid"], kinds[q["kind"]], q["budget"], q["u"], q["w"])
-        done = []
-        while not done:
-            srv.step(wait=True)
-            done = srv.poll()
-        bad += sum(r["status"] != 0 for r in done)
-    return time.perf_counter() - t0, bad
-
-
-def bench_large(lap, gg, peaks):
-    """Large plain run: R-MAT scale 22 (edge factor 16, a/b/c/d = .57/.19/.19/.05),
-    symmetrised, self-loops and duplicates dropped, largest component kept;
-    root = max degree; 512 trees plus 512 walks of each kind per step."""
-    import torch
-    t = time.perf_counter()
-    src, dst = gg.rmat(22, 16, seed=0)
-    g = lap.Graph(1 << 22, src, dst, keep_lcc=True)
-    del src, dst
-    log(f"large: R-MAT 22 LCC n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
-    dev = torch.device("cuda:0")
-    out = {k: torch.empty(g.n, dtype=torch.float64, device=dev) for k in ("diag", "diag_se", "closeness")}
-    out.update({k: torch.empty(1, dtype=torch.float64, device=dev) for k in ("trace", "kemeny", "kemeny_se")})
-    omega = 512
-    g.estimate(omega, 1, -1, B=64, out=out)
-    torch.cuda.synchronize()
-    lap.prof_reset()
-    lap.prof_enable(True)
-    reps = 2
-    t = time.perf_counter()
-    for _ in range(reps):
-        g.estimate(omega, 1, -1, B=64, out=out)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / reps
-    lap.prof_enable(False)
-    st = g.last_stats()
-    kern = "wilson_group" if lap.prof_read("wilson_group")[1] else "wilson_wave"
-    ms_w, n_w = lap.prof_read(kern)
-    wave_s = ms_w / max(n_w, 1) * 1e-3
-    loads = LOADS_PER_WILSON_STEP * st["wilson_steps"] / wave_s
-    res = {"workload": "R-MAT scale 22 LCC, root = max degree, 512 trees + 512 walks of each kind",
-           "n": g.n, "nnz": g.nnz, "omega": omega, "s_per_step": dt, "kernel": kern,
-           "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) / dt,
-           "trees_per_s": omega / dt, "wilson_steps_per_tree": st["wilson_steps"] / omega,
-           "wilson_kernel_s": wave_s, "wilson_loads_per_s": loads,
-           "state_bytes": 8 * g.n * omega,
-           "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
-    if peaks:
-        res["frac_of_chase_peak_4GiB"] = loads / peaks["4GiB"]["chase"]
-    g.close()
-    return res
-
-
-def bench_serve(lap, gg, n_queries):
-    """Serving: resident R-MAT scale-21 graph (edge factor 16, a/b/c/d =
-    .57/.19/.19/.05, symmetrised, self-loops and duplicates dropped, largest
-    component); Poisson arrivals mixing single-node closeness (64..1024 walks,
-    log-uniform), pairwise resistance (1024 walk pairs) and Kemeny (256
-    samples) in proportions 45/45/10.  Saturation throughput is measured with
-    every query submitted at once; latency percentiles at 50% and 80% of it."""
-    t = time.perf_counter()
-    src, dst = gg.rmat(21, 16, seed=0)
-    g = lap.Graph(1 << 21, src, dst, keep_lcc=True)
-    del src, dst
-    log(f"serve: R-MAT 21 LCC n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
-    srv = lap.Server(g, seed=1, global_samples=256)
-    qs = gg.query_stream(g.n, n_queries, qps=1.0, seed=3)
-    for q in qs:
-        q["t"] = 0.0
-    lat, wall, bad = _replay(lap, srv, qs, 0)
-    sat = n_queries / wall
-    log(f"serve: saturation {sat:.1f} queries/s")
-    n_serial = min(n_queries, 100)
-    wall_serial, bad_serial = _serial(lap, srv, qs[:n_serial], 10_000_000)
-    log(f"serve: one query at a time {n_serial / wall_serial:.1f} queries/s")
-    out = {"workload": "R-MAT scale 21 LCC resident; Poisson mix 45% closeness (64-1024 walks), "
-                       "45% resistance (1024 walk pairs), 10% Kemeny (256 samples)",
-           "n": g.n, "nnz": g.nnz, "queries": n_queries, "saturation_qps": sat,
-           "closed_loop_p50_ms": float(np.percentile(lat, 50) * 1e3), "errors": int(bad) + int(bad_serial),
-           "one_at_a_time_qps": n_serial / wall_serial,
-           "speedup_served_vs_one_at_a_time": sat / (n_serial / wall_serial), "runs": []}
-    for k, frac in enumerate((0.5, 0.8)):
-        qs = gg.query_stream(g.n, n_queries, qps=frac * sat, seed=4 + k)
-        lat, wall, bad = _replay(lap, srv, qs, (k + 1) * 1_000_000)
-        out["runs"].append({"offered_qps": frac * sat, "achieved_qps": n_queries / wall,
-                            "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                            "p99_ms": float(np.percentile(lat, 99) * 1e3), "errors": int(bad)})
-        log(f"serve: {frac:.0%} load p50 {out['runs'][-1]['p50_ms']:.1f} ms p99 {out['runs'][-1]['p99_ms']:.1f} ms")
-    srv.close()
-    g.close()
-    return out
 
 
 def main():
@@ -483,159 +729,123 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--omega", type=int, default=4096)
-    ap.add_argument("--no-gather", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--only", default="", help="comma-separated sections to run (default: all): " +
+                                               ",".join(SECTIONS))
+    ap.add_argument("--skip", default="", help="comma-separated sections to leave out")
     ap.add_argument("--batch-jobs", type=int, default=512)
-    ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--no-spantree", action="store_true")
-    ap.add_argument("--no-landmark", action="store_true")
-    ap.add_argument("--no-loop-paths", action="store_true")
-    ap.add_argument("--no-pairs", action="store_true")
-    ap.add_argument("--no-kc-families", action="store_true")
     ap.add_argument("--kc-n", type=int, default=100_000)
+    ap.add_argument("--kc-er-omega", type=int, default=4096)
     ap.add_argument("--serve-queries", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
     ap.add_argument("--write-traffic", metavar="DIR",
-                    help="only reduce the counter databases under DIR to the traffic summary and exit")
+                    help="only reduce the counter runs under DIR to a traffic summary and exit")
+    ap.add_argument("--traffic-of", default="large", choices=sorted(TRAFFIC))
     args = ap.parse_args()
     if args.write_traffic:
-        write_traffic(args.write_traffic)
+        write_traffic(args.write_traffic, args.traffic_of)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    only = set(filter(None, args.only.split(","))) or set(SECTIONS)
+    only -= set(filter(None, args.skip.split(",")))
+    unknown = only - set(SECTIONS)
+    if unknown:
+        raise SystemExit(f"unknown sections {sorted(unknown)}")
+    with_cpu = not args.no_cpu_baseline
 
-    import numpy as np
     import torch
 
     import graphgen as gg
     import paper_2311_10290_amd as lap
 
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
     if args.copy_calibration:
-        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")     # 1 GiB
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 8}), flush=True)
         return
-    n, m, omega, seed = 100_000, 5, args.omega, 1
-    log("generating BA(100000, 5)")
-    src, dst = gg.barabasi_albert(n, m, 0)
-    g = lap.Graph(n, src, dst)
-    root = g.max_deg_node
-    out = {k: torch.empty(g.n, dtype=torch.float64, device=dev) for k in ("diag", "diag_se", "closeness")}
-    out.update({k: torch.empty(1, dtype=torch.float64, device=dev) for k in ("trace", "kemeny", "kemeny_se")})
-    stream = torch.cuda.current_stream()
 
-    def step():
-        g.estimate(omega, seed, root, B=64, out=out, stream=stream)
-
-    for i in range(args.warmup):
-        step()
-        log(f"warmup {i + 1}/{args.warmup}")
-    torch.cuda.synchronize()
-    st = g.last_stats()
-    lap.prof_reset()
-    lap.prof_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-        log(f"step {i + 1}/{args.steps}")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    lap.prof_enable(False)
-    st = g.last_stats()
-    steps_per = st["wilson_steps"] + st["absorbed_steps"]
-    value = steps_per * args.steps / dt
-    ms_w, n_w = lap.prof_read("wilson_wave")
-    ms_a, n_a = lap.prof_read("absorbed")
-    ms_s, n_s = lap.prof_read("assemble")
-    wave_ms = ms_w / max(n_w, 1)
-    alg_bytes = WILSON_BYTES_PER_STEP * st["wilson_steps"] + RETRACE_BYTES_PER_NODE * g.n * st["trees"]
-    achieved = alg_bytes / (wave_ms * 1e-3) / 1e9
-    res = {
-        "metric": "walk steps/s & spanning trees/s at 1 GPU, batched vs plain; p99 query latency",
-        "value": value,
-        "unit": "walk steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64 counts, f64 estimates",
-        "data": "synthetic (seeded Barabasi-Albert graph; no dataset)",
-        "config": {"workload": "plain LEWalk closeness + Kemeny: Barabasi-Albert n=100000 m=5, "
-                               "root=max degree, omega=4096 trees, Philox seed 1",
-                   "n": g.n, "nnz": g.nnz, "omega": omega, "mode": "wave"},
-        "trees_per_s": omega * args.steps / dt,
-        "wilson_steps_per_step": st["wilson_steps"],
-        "wave_iterations_per_step": st["iterations"], "cycle_pops": st["pops"], "rescans": st["rescans"],
-        "absorbed_steps_per_step": st["absorbed_steps"],
-        "kernel_ms": {"wilson_wave": wave_ms, "absorbed": ms_a / max(n_a, 1),
-                      "assemble": ms_s / max(n_s, 1)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "wilson_wave_kernel",
-                     "bytes_per_launch": alg_bytes},
-        "estimates": {"kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item()),
-                      "trace_Ldagger": float(out["trace"].item())},
-    }
-    peaks = {}
-    if not args.no_gather:
-        log("random-gather peak")
-        lanes = 256 * 24 * 64
-        for label, nbytes in (("4MiB", 4 << 20), ("128MiB", 128 << 20), ("4GiB", 4 << 30)):
-            peaks[label] = {"chase": lap.bench_gather(nbytes, lanes, 1),
-                            "independent": lap.bench_gather(nbytes, lanes // 4, 0)}
-        loads = LOADS_PER_WILSON_STEP * st["wilson_steps"]
-        achieved_loads = loads / (wave_ms * 1e-3)
-        res["gather"] = {"loads_per_wilson_step": LOADS_PER_WILSON_STEP,
-                         "achieved_loads_per_s": achieved_loads,
-                         "peak_loads_per_s": peaks,
-                         "frac_of_chase_peak_4GiB": achieved_loads / peaks["4GiB"]["chase"],
-                         "state_bytes": 8 * g.n * min(omega, 4096)}
-        # line fetches: every 4 GiB chase load fetches one 128-byte line
-        # (FETCH_SIZE); the kernel's fetched bytes come from its counter summary
-        fetch = measured_traffic("FETCH_SIZE")
-        chase_line = peaks["4GiB"]["chase"] * CHASE_BYTES_PER_LOAD
-        res["gather"]["chase_line_bytes_per_s_4GiB"] = chase_line
-        res["gather"]["wilson_fetch_bytes_per_s"] = fetch / (wave_ms * 1e-3) if fetch else None
-        res["gather"]["frac_of_chase_line_rate"] = fetch / (wave_ms * 1e-3) / chase_line if fetch else None
-    if not args.no_spantree:
+    res = {"metric": "walk steps/s & spanning trees/s at 1 GPU, batched vs plain; p99 query latency",
+           "unit": "walk steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int64 counts, f64 estimates",
+           "data": "synthetic (seeded R-MAT, Erdos-Renyi, Barabasi-Albert and hyperbolic graphs; no dataset)"}
+    gather = None
+    if "gather" in only:
+        log("random-gather sweep")
+        gather = bench_gather(lap)
+    if "large" in only:
+        g, src, dst = rmat_graph(lap, gg, 22)
+        omega = 512
+        log(f"large: {args.warmup} warm-up + {args.steps} timed steps")
+        dt, st, kern, wk, out = timed_steps(lap, g, omega, -1, args.steps, args.warmup)
+        kms = kern[wk]["ms_avg"]
+        traffic = measured_traffic("large")
+        res.update({
+            "value": (st["wilson_steps"] + st["absorbed_steps"]) * args.steps / dt,
+            "ms_per_step": dt * 1e3 / args.steps,
+            "config": {"workload": "plain LEWalk closeness + Kemeny: R-MAT scale 22 (edge factor 16, "
+                                   "a/b/c/d .57/.19/.19/.05) symmetrised, largest component, root = max degree, "
+                                   "omega = 512 trees, B = 64, Philox seed 1",
+                       "n": g.n, "nnz": g.nnz, "omega": omega, "wilson_kernel": TRAFFIC["large"]["kernel"]},
+            "trees_per_s": omega * args.steps / dt,
+            "wilson_steps_per_step": st["wilson_steps"], "absorbed_steps_per_step": st["absorbed_steps"],
+            "wilson_steps_per_tree_over_n": st["wilson_steps"] / omega / g.n,
+            "kernel_ms": {k: v["ms_avg"] for k, v in kern.items()},
+            "roofline": roofline(st, g.n, kms, traffic, TRAFFIC["large"]["kernel"]),
+            "requests": request_rate(traffic, kms, gather),
+            "estimates": {"kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item()),
+                          "trace_Ldagger": float(out["trace"].item())},
+        })
+        log(f"large: {res['ms_per_step']:.2f} ms per step, {res['value'] / 1e9:.2f} G walk steps/s, "
+            f"Wilson {kms:.2f} ms")
+        root = g.max_deg_node
+        g.close()
+        if with_cpu:
+            log("large: cpu baseline (oracle)")
+            from oracle import csr as ocsr
+            og = ocsr.build_csr(1 << 22, src, dst, keep_lcc=True)
+            res["cpu_baseline"] = cpu_baseline(og, root, omega, budget_s=15.0, probe=16)
+            del og
+        del src, dst
+    if "small" in only:
+        log("small workload")
+        res["small"] = bench_small(lap, gg, with_cpu, gather)
+    mid = None
+    if only & {"mid", "spantree", "loop_paths", "pairs"}:
+        log("mid workload")
+        r_mid, g_mid, root_mid = bench_mid(lap, gg, args.steps, args.warmup, with_cpu and "mid" in only, gather)
+        if "mid" in only:
+            res["mid"] = r_mid
+        mid = (g_mid, root_mid)
+    if "spantree" in only:
         log("spantree")
-        res["spantree"] = bench_spantree(lap, g, root, 1024)
-    if not args.no_loop_paths:
+        res["spantree"] = bench_spantree(lap, mid[0], mid[1], 1024)
+    if "loop_paths" in only:
         log("loop-included paths")
-        res["loop_paths"] = bench_loop_paths(lap, g, root, omega)
-    if not args.no_pairs:
+        res["loop_paths"] = bench_loop_paths(lap, mid[0], mid[1], 4096)
+    if "pairs" in only:
         log("node-pair paths")
-        res["pairs"] = bench_pairs(lap, g, root, n)
-    if not args.no_landmark:
+        res["pairs"] = bench_pairs(lap, mid[0], mid[1], mid[0].n)
+    if mid:
+        mid[0].close()
+    if "landmark" in only:
         log("landmark study")
         res["landmark"] = bench_landmark(lap, gg)
-    if not args.no_kc_families:
+    if "kc_families" in only:
         log("Kemeny's constant of synthetic families")
-        res["kc_families"] = bench_kc_families(lap, gg, args.kc_n)
-    if not args.no_batch:
-        res["batched"] = bench_batch(lap, gg, args.batch_jobs)
-    if not args.no_serve:
-        res["serving"] = bench_serve(lap, gg, args.serve_queries)
-    if not args.no_large:
-        res["large"] = bench_large(lap, gg, peaks if not args.no_gather else None)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        from oracle import csr as ocsr
-        og = ocsr.build_csr(n, src, dst)
-        res["cpu_baseline"] = cpu_baseline(og, root, omega, seed)
+        res["kc_families"] = bench_kc_families(lap, gg, args.kc_n, args.kc_er_omega)
+    if "batched" in only:
+        res["batched"] = bench_batch(lap, gg, args.batch_jobs, with_cpu)
+    if "serving" in only:
+        res["serving"] = bench_serve(lap, gg, args.serve_queries, with_cpu)
+    if gather:
+        res["gather"] = gather
     print(json.dumps(res), flush=True)
 
 

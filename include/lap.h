@@ -256,7 +256,7 @@ int lap_batch_job_info(const lap_batch *b, int32_t job, int64_t *n, int64_t *nnz
  * captured once per tuning on an internal stream and replayed. */
 int lap_batch_run(lap_batch *b, const lap_batch_tuning *t, void *hip_stream);
 /* Time a grid of pool sizes (8, 16, 24 waves per CU) and chunk sizes (2^15,
- * 2^17, 2^19) on the whole batch, after one untimed warm-up run, and return
+ * 2^17 node-samples per Wilson item) on the whole batch, after one untimed warm-up run, and return
  * (with use_graph set) the largest pool among the tunings within 3% of the
  * fastest, at its fastest chunk size; *best_ms is that tuning's time.  When
  * the batch is a probe subset of a larger one, the larger pool is the safer
@@ -524,13 +524,19 @@ int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_
                    int64_t *trees, int64_t *iterations, int64_t *pops, int64_t *rescans,
                    int64_t *idle_lane_rounds, int64_t *parked_lane_rounds);
 
-/* Random-gather peak of the current device, the roofline reference for the
+/* Random-gather rate of the current device, the roofline reference for the
  * walkers: loads per second (written to *rate) of random 8-byte loads over a
  * working set of `bytes` (>= 1 MiB, rounded down to a power of two) by
- * `lanes` (>= 64) concurrent lanes; mode 0 = independent loads, 1 = each
- * lane follows a dependent pointer chain through a random cyclic order of
- * 64-byte lines.  Allocates and frees its own buffer. */
-int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, double *rate, void *hip_stream);
+ * `lanes` (256 .. 2^24) concurrent lanes.  mode 0: each lane issues
+ * `in_flight` (1, 2, 4, 8 or 16) independent loads per round; mode 1: each lane
+ * follows a dependent pointer chain through a random cyclic order of 64-byte
+ * lines (in_flight must be 1, 2, 4, 8 or 16 and is ignored).  flavor: 0 plain
+ * loads, 1 non-temporal loads, 2 relaxed atomic loads at device scope, 3 at
+ * system scope.  A sweep over lanes and in_flight gives each working-set
+ * tier's peak.  Allocates and frees its own buffer; LAP_EINVAL on bad
+ * arguments. */
+int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int32_t in_flight, int32_t flavor,
+                     double *rate, void *hip_stream);
 
 #ifdef __cplusplus
 }

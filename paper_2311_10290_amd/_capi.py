@@ -109,7 +109,7 @@ def declare(lib):
         "lap_prof_reset": ([], i32),
         "lap_prof_read": ([ctypes.c_char_p, P, P], i32),
         "lap_last_stats": ([P, P, P, P, P, P, P, P, P], i32),
-        "lap_bench_gather": ([i64, i64, i32, P, P], i32),
+        "lap_bench_gather": ([i64, i64, i32, i32, i32, P, P], i32),
         "lap_batch_create": ([ctypes.POINTER(BatchJob), i32, P, P], i32),
         "lap_batch_job_info": ([P, i32, P, P, P], i32),
         "lap_batch_run": ([P, ctypes.POINTER(BatchTuning), P], i32),

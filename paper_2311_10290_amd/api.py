@@ -450,10 +450,13 @@ class Server:
                 raise TimeoutError("server did not drain")
 
 
-def bench_gather(bytes_, lanes, mode, stream=None):
-    """Random 8-byte loads per second over a working set (mode 0 independent, 1 chase)."""
+def bench_gather(bytes_, lanes, mode, in_flight=1, flavor=0, stream=None):
+    """Random 8-byte loads per second over a working set (mode 0 independent
+    with in_flight loads per lane and round, 1 chase); flavor 0 plain loads,
+    1 non-temporal, 2 / 3 relaxed atomic loads at device / system scope."""
     r = ctypes.c_double()
-    _check(load_library().lap_bench_gather(int(bytes_), int(lanes), int(mode), ctypes.byref(r), _stream(stream)))
+    _check(load_library().lap_bench_gather(int(bytes_), int(lanes), int(mode), int(in_flight), int(flavor),
+                                           ctypes.byref(r), _stream(stream)))
     return r.value
 
 

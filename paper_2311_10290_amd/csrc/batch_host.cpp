@@ -319,7 +319,7 @@ extern "C" int lap_batch_autotune(lap_batch *b, lap_batch_tuning *best, double *
     if (!b || !best) return fail(LAP_EINVAL, "batch or output is NULL");
     hipStream_t s = (hipStream_t)hip_stream;
     const int pools[] = {8, 16, 24};
-    const int chunks[] = {1 << 15, 1 << 17, 1 << 19};
+    const int chunks[] = {1 << 15, 1 << 17};   // 2^19 lost on every pool of the 512-graph batch
     // one untimed run at the largest pool: the walk state is allocated and
     // the device warmed before any candidate is timed
     {

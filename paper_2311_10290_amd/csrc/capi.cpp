@@ -262,33 +262,31 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         }
         HIP_TRY(hipEventRecord(g->ev_fork, s));
         HIP_TRY(hipStreamWaitEvent(g->aux, g->ev_fork, 0));
-        for (int kind = 1; kind <= 2; ++kind) {
-            if ((kind == 1 && !r.y2u) || (kind == 2 && !r.y2p)) continue;
-            AbsorbedParams ap;
-            std::memset(&ap, 0, sizeof ap);
-            ap.n = n;
-            ap.nbr = g->nbr.as<uint64_t>();
-            ap.col = g->col.as<int32_t>();
-            ap.arcs = (const ulonglong2 *)g->arcs.ptr;
-            ap.nnz = g->csr.rp[n];
-            ap.root = r.root;
-            ap.k0 = a->seed;
-            ap.k1 = k1;
-            ap.qid = a->qid;
-            ap.tag = (uint32_t)kind;
-            ap.walk_begin = r.begin;
-            ap.n_walks = r.omega;
-            ap.n_total = r.total;
-            ap.n_blocks = r.B;
-            ap.y2 = kind == 1 ? g->y2.as<unsigned long long>() : nullptr;
-            ap.len_out = kind == 1 ? g->len_u.as<int64_t>() : g->len_p.as<int64_t>();
-            ap.stats = g->stats.as<unsigned long long>();
-            ap.err = g->err.as<DevErr>();
-            ap.deadline = deadline;
-            tm.begin("absorbed", g->aux);
-            HIP_TRY(launch_absorbed(ap, g->aux));
-            tm.end(g->aux);
-        }
+        AbsorbedParams ap;
+        std::memset(&ap, 0, sizeof ap);
+        ap.n = n;
+        ap.nbr = g->nbr.as<uint64_t>();
+        ap.col = g->col.as<int32_t>();
+        ap.arcs = (const ulonglong2 *)g->arcs.ptr;
+        ap.nnz = g->csr.rp[n];
+        ap.root = r.root;
+        ap.k0 = a->seed;
+        ap.k1 = k1;
+        ap.qid = a->qid;
+        ap.kinds = (r.y2u ? 1u : 0u) | (r.y2p ? 2u : 0u);
+        ap.walk_begin = r.begin;
+        ap.n_walks = r.omega;
+        ap.n_total = r.total;
+        ap.n_blocks = r.B;
+        ap.y2 = r.y2u ? g->y2.as<unsigned long long>() : nullptr;
+        ap.len_u = r.y2u ? g->len_u.as<int64_t>() : nullptr;
+        ap.len_p = r.y2p ? g->len_p.as<int64_t>() : nullptr;
+        ap.stats = g->stats.as<unsigned long long>();
+        ap.err = g->err.as<DevErr>();
+        ap.deadline = deadline;
+        tm.begin("absorbed", g->aux);
+        HIP_TRY(launch_absorbed(ap, g->aux));
+        tm.end(g->aux);
         HIP_TRY(hipEventRecord(g->ev_join, g->aux));
     }
     if (r.wilson) {

@@ -20,28 +20,38 @@
 
 namespace lap {
 
+// Both walk kinds in one grid (blockIdx.y picks the kind), so a step waits for
+// the longer of the two longest walks, not their sum.  The walks are few
+// single-lane chains that overlap the Wilson kernel on the same CUs; they run
+// at raised wave priority so each of their dependent steps issues promptly.
 __global__ __launch_bounds__(64) void absorbed_kernel(AbsorbedParams p) {
+    __builtin_amdgcn_s_setprio(3);
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const uint64_t t0 = wall_clock64();
+    const uint32_t tag = (p.kinds == 2 || blockIdx.y == 1) ? 2u : 1u;
+    unsigned long long *y2 = tag == 1 ? p.y2 : nullptr;
+    int64_t *len_out = tag == 1 ? p.len_u : p.len_p;
     const WalkGraph g{p.nbr, p.col, p.arcs, p.n, p.nnz, p.root, p.k0, p.k1, p.qid};
     unsigned long long steps = 0;
     for (int64_t wi = gid; wi < p.n_walks; wi += stride) {
         const int64_t i = p.walk_begin + wi;
-        unsigned long long *y2b = p.y2 ? p.y2 + ((i * (int64_t)p.n_blocks) / p.n_total) * p.n : nullptr;
-        const int64_t len = absorbed_walk(g, p.tag, i, y2b, p.err, t0, p.deadline);
+        unsigned long long *y2b = y2 ? y2 + ((i * (int64_t)p.n_blocks) / p.n_total) * p.n : nullptr;
+        const int64_t len = absorbed_walk(g, tag, i, y2b, p.err, t0, p.deadline);
         if (len < 0) break;
-        if (p.len_out) p.len_out[wi] = len;
+        if (len_out) len_out[wi] = len;
         steps += (unsigned long long)len;
     }
     atomicAdd(&p.stats[kStatAbsorbed], steps);
 }
 
 hipError_t launch_absorbed(const AbsorbedParams &p, hipStream_t s) {
+    if (p.kinds < 1 || p.kinds > 3) return hipErrorInvalidValue;
     const int bs = 64;
     int64_t grid = (p.n_walks + bs - 1) / bs;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(absorbed_kernel, dim3((unsigned)grid), dim3(bs), 0, s, p);
+    const unsigned n_kinds = p.kinds == 3 ? 2u : 1u;
+    hipLaunchKernelGGL(absorbed_kernel, dim3((unsigned)grid, n_kinds), dim3(bs), 0, s, p);
     return hipGetLastError();
 }
 

@@ -1,15 +1,21 @@
-// Random-gather peak of the device, the roofline the walkers are compared
+// Random-gather rates of the device, the roofline the walkers are compared
 // against: walker steps are chains of dependent 4-8 byte loads at random
 // addresses, so neither streaming bandwidth nor MFMA rate bounds them.
 //
-//   independent: every lane issues 8 independent random 8-byte loads per
-//                round (addresses from a hash of lane and round), so the
-//                memory system sees as many requests as it will accept;
+//   independent: every lane issues `in_flight` independent random 8-byte loads
+//                per round (addresses from a hash of lane and round), so the
+//                memory system sees up to lanes x in_flight requests at once;
 //   chase:       every lane follows its own pointer chain through a random
 //                cyclic order of 64-byte lines (one dependent load per hop),
 //                the access pattern of a walker.
 // Both report loads per second over a working set of the given size, which
-// selects the cache tier (L2 4 MB per XCD, 256 MB Infinity Cache, HBM).
+// selects the cache tier (L2 4 MB per XCD, 256 MB Infinity Cache, HBM).  A
+// sweep over lanes (and loads in flight) gives the peak of each tier.
+//
+// flavor selects how the loads are issued: 0 plain loads, 1 non-temporal
+// loads, 2 relaxed atomic loads at device scope, 3 relaxed atomic loads at
+// system scope (the cache policy bits differ; the rate and the bytes each
+// load fetches from memory show which suits scattered 8-byte words).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,46 +30,95 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+template <int F>
+__device__ __forceinline__ uint64_t load_word(const uint64_t *p) {
+    if constexpr (F == 1) {
+        return __builtin_nontemporal_load(p);
+    } else if constexpr (F == 2) {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if constexpr (F == 3) {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+        return *p;
+    }
+}
+
 // line i (8 words) holds in word 0 the index of the next line of the chain:
 // next = (a * i + c) mod n_lines with n_lines a power of two, a = 5 mod 8,
-// c odd, a full-period permutation, then scrambled by xor with a mask.
+// c odd: a full-period permutation.
 __global__ void chase_init_kernel(uint64_t *buf, uint64_t n_lines, uint64_t a, uint64_t c) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_lines; i += stride)
         buf[i * 8] = (a * i + c) & (n_lines - 1);
 }
 
+template <int F>
 __global__ __launch_bounds__(256) void chase_kernel(const uint64_t *buf, uint64_t n_lines, int64_t hops,
                                                     uint64_t *sink) {
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t p = mix64(gid) & (n_lines - 1);
-    for (int64_t h = 0; h < hops; ++h) p = buf[p * 8];
+    for (int64_t h = 0; h < hops; ++h) p = load_word<F>(buf + p * 8) & (n_lines - 1);
     if (p == 0xFFFFFFFFFFFFFFFFull) sink[0] = p;
 }
 
+template <int D, int F>
 __global__ __launch_bounds__(256) void gather_kernel(const uint64_t *buf, uint64_t n_words, int64_t rounds,
                                                      uint64_t *sink) {
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t acc = 0;
     for (int64_t r = 0; r < rounds; ++r) {
-        uint64_t v[8];
+        uint64_t v[D];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = buf[mix64(gid * 0x9E3779B97F4A7C15ull + (uint64_t)r * 8 + j) & (n_words - 1)];
+        for (int j = 0; j < D; ++j)
+            v[j] = load_word<F>(buf + (mix64(gid * 0x9E3779B97F4A7C15ull + (uint64_t)r * D + j) & (n_words - 1)));
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc ^= v[j];
+        for (int j = 0; j < D; ++j) acc ^= v[j];
     }
     if (acc == 0x1234567) sink[0] = acc;
+}
+
+template <int F>
+void launch_gather_depth(int depth, unsigned grid, hipStream_t s, const uint64_t *buf, uint64_t words,
+                         int64_t rounds, uint64_t *sink) {
+    switch (depth) {
+        case 1: hipLaunchKernelGGL((gather_kernel<1, F>), dim3(grid), dim3(256), 0, s, buf, words, rounds, sink); break;
+        case 2: hipLaunchKernelGGL((gather_kernel<2, F>), dim3(grid), dim3(256), 0, s, buf, words, rounds, sink); break;
+        case 4: hipLaunchKernelGGL((gather_kernel<4, F>), dim3(grid), dim3(256), 0, s, buf, words, rounds, sink); break;
+        case 8: hipLaunchKernelGGL((gather_kernel<8, F>), dim3(grid), dim3(256), 0, s, buf, words, rounds, sink); break;
+        default: hipLaunchKernelGGL((gather_kernel<16, F>), dim3(grid), dim3(256), 0, s, buf, words, rounds, sink); break;
+    }
+}
+
+void launch_gather(int flavor, int depth, unsigned grid, hipStream_t s, const uint64_t *buf, uint64_t words,
+                   int64_t rounds, uint64_t *sink) {
+    switch (flavor) {
+        case 1: launch_gather_depth<1>(depth, grid, s, buf, words, rounds, sink); break;
+        case 2: launch_gather_depth<2>(depth, grid, s, buf, words, rounds, sink); break;
+        case 3: launch_gather_depth<3>(depth, grid, s, buf, words, rounds, sink); break;
+        default: launch_gather_depth<0>(depth, grid, s, buf, words, rounds, sink); break;
+    }
+}
+
+void launch_chase(int flavor, unsigned grid, hipStream_t s, const uint64_t *buf, uint64_t n_lines, int64_t hops,
+                  uint64_t *sink) {
+    switch (flavor) {
+        case 1: hipLaunchKernelGGL(chase_kernel<1>, dim3(grid), dim3(256), 0, s, buf, n_lines, hops, sink); break;
+        case 2: hipLaunchKernelGGL(chase_kernel<2>, dim3(grid), dim3(256), 0, s, buf, n_lines, hops, sink); break;
+        case 3: hipLaunchKernelGGL(chase_kernel<3>, dim3(grid), dim3(256), 0, s, buf, n_lines, hops, sink); break;
+        default: hipLaunchKernelGGL(chase_kernel<0>, dim3(grid), dim3(256), 0, s, buf, n_lines, hops, sink); break;
+    }
 }
 
 }  // namespace lap
 
 using namespace lap;
 
-// bytes: working set (rounded down to a power of two, >= 1 MiB); lanes: number
-// of concurrent lanes; mode 0 = independent gathers, 1 = pointer chase.
-// Returns loads per second in *rate.
-extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, double *rate, void *hip_stream) {
-    if (bytes < (1 << 20) || lanes < 64 || !rate || (mode != 0 && mode != 1)) return LAP_EINVAL;
+extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int32_t in_flight, int32_t flavor,
+                                double *rate, void *hip_stream) {
+    if (bytes < (1 << 20) || lanes < 256 || lanes > ((int64_t)1 << 24) || !rate || (mode != 0 && mode != 1) ||
+        (in_flight != 1 && in_flight != 2 && in_flight != 4 && in_flight != 8 && in_flight != 16) || flavor < 0 ||
+        flavor > 3)
+        return LAP_EINVAL;
     uint64_t words = 1;
     while (words * 2 * 8 <= (uint64_t)bytes) words *= 2;
     hipStream_t s = (hipStream_t)hip_stream;
@@ -78,22 +133,23 @@ extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, doub
     hipLaunchKernelGGL(chase_init_kernel, dim3(4096), dim3(256), 0, s, buf, n_lines, 0x5DEECE66Dull * 8 + 5,
                        0x2545F4914F6CDD1Dull | 1ull);
     const unsigned grid = (unsigned)((lanes + 255) / 256);
-    const int64_t work = mode == 0 ? 64 : 512;   // rounds (x8 loads) or hops per lane
+    // work per lane: rounds of in_flight loads, or hops, about 512 loads either way
+    const int64_t work = mode == 0 ? 512 / in_flight : 512;
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
     for (int rep = 0; rep < 2; ++rep) {           // first pass warms the caches
         (void)hipEventRecord(a, s);
         if (mode == 0)
-            hipLaunchKernelGGL(gather_kernel, dim3(grid), dim3(256), 0, s, buf, words, work, sink);
+            launch_gather(flavor, in_flight, grid, s, buf, words, work, sink);
         else
-            hipLaunchKernelGGL(chase_kernel, dim3(grid), dim3(256), 0, s, buf, n_lines, work, sink);
+            launch_chase(flavor, grid, s, buf, n_lines, work, sink);
         (void)hipEventRecord(b, s);
     }
-    if (hipEventSynchronize(b) != hipSuccess) rc = LAP_EDEVICE;
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(b) != hipSuccess) rc = LAP_EDEVICE;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
-    const double loads = (double)grid * 256.0 * (double)work * (mode == 0 ? 8.0 : 1.0);
+    const double loads = (double)grid * 256.0 * (double)work * (mode == 0 ? (double)in_flight : 1.0);
     *rate = ms > 0 ? loads / (ms * 1e-3) : 0.0;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);

@@ -143,11 +143,11 @@ struct AbsorbedParams {
     int64_t nnz;
     int32_t root;
     uint64_t k0, k1, qid;
-    uint32_t tag;                  // 1 uniform start, 2 stationary start
+    uint32_t kinds;                // bit 0: uniform-start walks (tag 1), bit 1: stationary-start walks (tag 2)
     int64_t walk_begin, n_walks, n_total;
     int32_t n_blocks;
-    unsigned long long *y2;        // [B][n] or null
-    int64_t *len_out;              // [n_walks] or null
+    unsigned long long *y2;        // [B][n] visits of the uniform-start walks, or null
+    int64_t *len_u, *len_p;        // [n_walks] lengths of each kind, or null
     unsigned long long *stats;
     DevErr *err;
     uint64_t deadline;

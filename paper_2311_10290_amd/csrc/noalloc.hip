@@ -128,8 +128,7 @@ extern "C" int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a
     const uint64_t k1 = ((uint64_t)a->stream << 32) | (uint64_t)(uint32_t)r.root;
 
     // absorbed walks on the caller's stream (no auxiliary stream is created)
-    for (int kind = 1; kind <= 2; ++kind) {
-        if ((kind == 1 && !r.y2u) || (kind == 2 && !r.y2p)) continue;
+    if (r.y2u || r.y2p) {
         AbsorbedParams ap;
         std::memset(&ap, 0, sizeof ap);
         ap.n = n;
@@ -141,13 +140,14 @@ extern "C" int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a
         ap.k0 = a->seed;
         ap.k1 = k1;
         ap.qid = a->qid;
-        ap.tag = (uint32_t)kind;
+        ap.kinds = (r.y2u ? 1u : 0u) | (r.y2p ? 2u : 0u);
         ap.walk_begin = r.begin;
         ap.n_walks = r.omega;
         ap.n_total = r.total;
         ap.n_blocks = r.B;
-        ap.y2 = kind == 1 ? reinterpret_cast<unsigned long long *>(out->y2) : nullptr;
-        ap.len_out = kind == 1 ? out->y2len_uniform : out->y2len_pi;
+        ap.y2 = r.y2u ? reinterpret_cast<unsigned long long *>(out->y2) : nullptr;
+        ap.len_u = r.y2u ? out->y2len_uniform : nullptr;
+        ap.len_p = r.y2p ? out->y2len_pi : nullptr;
         ap.stats = stats;
         ap.err = err;
         ap.deadline = deadline;

@@ -236,6 +236,6 @@ def test_profiling_counters():
     ms, cnt = prof_read("wilson_wave")
     assert cnt == 1 and ms > 0
     ms, cnt = prof_read("absorbed")
-    assert cnt == 2 and ms > 0
+    assert cnt == 1 and ms > 0          # both walk kinds in one launch
     st = hg.last_stats()
     assert st["trees"] == 256 and st["wilson_steps"] > 0 and st["absorbed_steps"] > 0
