@@ -43,9 +43,9 @@ KERNEL_SOURCES = ["paper_2311_10290_amd/csrc/" + f for f in
                    "lap_launch.h", "lap_host.h", "capi.cpp")]
 TRAFFIC = {
     "large": dict(file="profiles/traffic_wilson_group_rmat22.json", kernel="wilson_group_kernel<8, true>",
-                  workload="R-MAT scale 22 LCC, omega=512, one launch"),
+                  workload="R-MAT scale 22 LCC numbered by decreasing degree, omega=512, one launch"),
     "mid": dict(file="profiles/traffic_wilson_wave_ba100k.json", kernel="wilson_wave_kernel<false>",
-                workload="Barabasi-Albert n=100000 m=5, omega=4096, one launch"),
+                workload="Barabasi-Albert n=100000 m=5 numbered by decreasing degree, omega=4096, one launch"),
 }
 SECTIONS = ("large", "small", "mid", "gather", "spantree", "loop_paths", "pairs", "landmark", "kc_families",
             "batched", "serving")
@@ -250,7 +250,7 @@ def request_rate(traffic, kern_ms, gather):
 def rmat_graph(lap, gg, scale):
     t = time.perf_counter()
     src, dst = gg.rmat(scale, 16, seed=0)
-    g = lap.Graph(1 << scale, src, dst, keep_lcc=True)
+    g = lap.Graph(1 << scale, src, dst, keep_lcc=True, degree_order=True)
     log(f"R-MAT {scale} LCC n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
     return g, src, dst
 
@@ -318,12 +318,13 @@ def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
     max degree, omega = 4096 (wave form)."""
     n, m, omega = 100_000, 5, 4096
     src, dst = gg.barabasi_albert(n, m, 0)
-    g = lap.Graph(n, src, dst)
+    g = lap.Graph(n, src, dst, degree_order=True)
     root = g.max_deg_node
     dt, st, kern, wk, out = timed_steps(lap, g, omega, root, steps, warmup)
     kms = kern[wk]["ms_avg"]
     traffic = measured_traffic("mid")
-    res = {"workload": "Barabasi-Albert n=100000 m=5, root = max degree, omega = 4096",
+    res = {"workload": "Barabasi-Albert n=100000 m=5 numbered by decreasing degree, root = max degree, "
+                       "omega = 4096",
            "n": g.n, "nnz": g.nnz, "omega": omega, "s_per_step": dt / steps,
            "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) * steps / dt,
            "trees_per_s": omega * steps / dt, "wilson_steps_per_step": st["wilson_steps"],
@@ -334,7 +335,8 @@ def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
            "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
     if with_cpu:
         from oracle import csr as ocsr
-        res["cpu_baseline"] = cpu_baseline(ocsr.build_csr(n, src, dst), root, omega, budget_s=10.0)
+        res["cpu_baseline"] = cpu_baseline(ocsr.build_csr(n, src, dst, degree_order=True), root, omega,
+                                           budget_s=10.0)
     return res, g, root
 
 
@@ -498,7 +500,7 @@ def bench_serve(lap, gg, n_queries, with_cpu, repeats=3):
     n_serial = min(n_queries, 100)
     wall_serial, bad_serial = _serial(lap, srv, qs[:n_serial], 10_000_000)
     log(f"serve: one query at a time {n_serial / wall_serial:.1f} queries/s")
-    res = {"workload": "R-MAT scale 21 LCC resident; Poisson mix 45% closeness (64-1024 walks), "
+    res = {"workload": "R-MAT scale 21 LCC (numbered by decreasing degree) resident; Poisson mix 45% closeness (64-1024 walks), "
                        "45% resistance (1024 walk pairs), 10% Kemeny (256 samples)",
            "n": g.n, "nnz": g.nnz, "queries": n_queries, "saturation_qps": sat,
            "closed_loop": _latency_summary(out_sat),
@@ -527,7 +529,7 @@ def serve_cpu(gg, g, src, dst, budget_s=12.0):
     (closeness and resistance walks on one thread, Kemeny samples on all
     cores), as a reference for the served latencies."""
     from oracle import csr as ocsr, native
-    og = ocsr.build_csr(1 << 21, src, dst, keep_lcc=True)
+    og = ocsr.build_csr(1 << 21, src, dst, keep_lcc=True, degree_order=True)
     root = ocsr.landmark(og)
     threads = oracle_threads()
     qs = gg.query_stream(og.n, 200, qps=1.0, seed=3)
@@ -790,8 +792,8 @@ def main():
             "value": (st["wilson_steps"] + st["absorbed_steps"]) * args.steps / dt,
             "ms_per_step": dt * 1e3 / args.steps,
             "config": {"workload": "plain LEWalk closeness + Kemeny: R-MAT scale 22 (edge factor 16, "
-                                   "a/b/c/d .57/.19/.19/.05) symmetrised, largest component, root = max degree, "
-                                   "omega = 512 trees, B = 64, Philox seed 1",
+                                   "a/b/c/d .57/.19/.19/.05) symmetrised, largest component numbered by "
+                                   "decreasing degree, root = max degree, omega = 512 trees, B = 64, Philox seed 1",
                        "n": g.n, "nnz": g.nnz, "omega": omega, "wilson_kernel": TRAFFIC["large"]["kernel"]},
             "trees_per_s": omega * args.steps / dt,
             "wilson_steps_per_step": st["wilson_steps"], "absorbed_steps_per_step": st["absorbed_steps"],
@@ -809,7 +811,7 @@ def main():
         if with_cpu:
             log("large: cpu baseline (oracle)")
             from oracle import csr as ocsr
-            og = ocsr.build_csr(1 << 22, src, dst, keep_lcc=True)
+            og = ocsr.build_csr(1 << 22, src, dst, keep_lcc=True, degree_order=True)
             res["cpu_baseline"] = cpu_baseline(og, root, omega, budget_s=15.0, probe=16)
             del og
         del src, dst

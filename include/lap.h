@@ -55,7 +55,7 @@ typedef enum {
 
 typedef struct lap_graph lap_graph;
 
-enum { LAP_KEEP_LCC = 1 };
+enum { LAP_KEEP_LCC = 1, LAP_DEGREE_ORDER = 2 };
 
 /*
  * lap_build_csr -- graph preparation (precondition of Sec. 2: simple,
@@ -64,9 +64,14 @@ enum { LAP_KEEP_LCC = 1 };
  * repeated pairs (in either orientation) merged.  If the result is not
  * connected: with LAP_KEEP_LCC the largest component is kept (ties: the one
  * holding the smallest id) and renumbered by ascending original id,
- * otherwise LAP_ENOTCONN.  Neighbour lists are sorted ascending.  The CSR
- * (row offsets int64[n+1], columns int32[2m]) is uploaded to the device
- * current at the call.  *out receives a new handle.
+ * otherwise LAP_ENOTCONN.  With LAP_DEGREE_ORDER the kept nodes are then
+ * numbered by decreasing degree, ties by increasing original id: the same
+ * graph under a layout where hubs share cache lines and walkers started one
+ * after another read neighbouring rows.  Node ids of every later call and
+ * output are the final numbering; lap_graph_copy_csr's old_ids maps them back.
+ * Neighbour lists are sorted ascending.  The CSR (row offsets int64[n+1],
+ * columns int32[2m]) is uploaded to the device current at the call.  *out
+ * receives a new handle.
  */
 int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst,
                   uint32_t flags, void *hip_stream, lap_graph **out);
@@ -219,7 +224,7 @@ typedef struct {
     int64_t n_edges;
     const int32_t *src;      /* host arrays, as for lap_build_csr */
     const int32_t *dst;
-    uint32_t flags;          /* LAP_KEEP_LCC */
+    uint32_t flags;          /* LAP_KEEP_LCC | LAP_DEGREE_ORDER */
     int32_t root;            /* -1 = highest-degree node */
     int64_t n_samples;       /* omega >= 1 */
     uint64_t seed;

@@ -8,7 +8,9 @@ this module builds that graph in CSR form with plain numpy/scipy steps:
   3. optionally keep only the largest connected component (ties: the
      component holding the smallest node id) and renumber its nodes by
      ascending original id; otherwise a disconnected graph is an error;
-  4. rows list neighbours in ascending order.
+  4. optionally (degree_order) number the nodes by decreasing degree, ties
+     by increasing id after step 3 -- a relabelling of the same graph;
+  5. rows list neighbours in ascending order.
 Landmark: the node of maximum degree, lowest id on ties.
 """
 from __future__ import annotations
@@ -40,7 +42,7 @@ class NotConnected(ValueError):
     pass
 
 
-def build_csr(n, src, dst, keep_lcc=False) -> Graph:
+def build_csr(n, src, dst, keep_lcc=False, degree_order=False) -> Graph:
     src = np.asarray(src, np.int64)
     dst = np.asarray(dst, np.int64)
     if src.shape != dst.shape:
@@ -72,6 +74,15 @@ def build_csr(n, src, dst, keep_lcc=False) -> Graph:
         m = (newid[u] >= 0) & (newid[v] >= 0)
         u, v = newid[u[m]], newid[v[m]]
         n = len(old_ids)
+    if degree_order:
+        deg = np.bincount(u, minlength=n)
+        order = np.lexsort((np.arange(n), -deg))     # by degree descending, then id
+        rank = np.empty(n, np.int64)
+        rank[order] = np.arange(n)
+        u, v = rank[u], rank[v]
+        key = np.sort(u * n + v)                       # rows ascending again
+        u, v = key // n, key % n
+        old_ids = old_ids[order]
     rp = np.zeros(n + 1, np.int64)
     np.add.at(rp, u + 1, 1)
     rp = np.cumsum(rp)

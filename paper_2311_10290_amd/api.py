@@ -88,15 +88,15 @@ def prof_read(kernel):
 class Graph:
     """A prepared graph resident on the current HIP device (lap_build_csr)."""
 
-    def __init__(self, n, src, dst, keep_lcc=False, stream=None):
+    def __init__(self, n, src, dst, keep_lcc=False, degree_order=False, stream=None):
         lib = load_library()
         src = np.ascontiguousarray(src, np.int32)
         dst = np.ascontiguousarray(dst, np.int32)
         if src.shape != dst.shape:
             raise ValueError("src and dst differ in length")
         h = ctypes.c_void_p()
-        _check(lib.lap_build_csr(int(n), len(src), _ptr(src), _ptr(dst),
-                                 C.LAP_KEEP_LCC if keep_lcc else 0, _stream(stream), ctypes.byref(h)))
+        flags = (C.LAP_KEEP_LCC if keep_lcc else 0) | (C.LAP_DEGREE_ORDER if degree_order else 0)
+        _check(lib.lap_build_csr(int(n), len(src), _ptr(src), _ptr(dst), flags, _stream(stream), ctypes.byref(h)))
         self._h = h
         n_ = ctypes.c_int64()
         nnz = ctypes.c_int64()
@@ -319,7 +319,8 @@ class Batch:
             d = np.ascontiguousarray(j["dst"], np.int32)
             self._keep += [s, d]
             arr[i] = C.BatchJob(n=int(j["n"]), n_edges=len(s), src=_ptr(s), dst=_ptr(d),
-                                flags=C.LAP_KEEP_LCC if j.get("keep_lcc") else 0, root=int(j.get("root", -1)),
+                                flags=(C.LAP_KEEP_LCC if j.get("keep_lcc") else 0)
+                                | (C.LAP_DEGREE_ORDER if j.get("degree_order") else 0), root=int(j.get("root", -1)),
                                 n_samples=int(j["omega"]), seed=int(j.get("seed", 1)),
                                 stream=int(j.get("stream_id", 0)), qid=int(j.get("qid", 0)))
         h = ctypes.c_void_p()

@@ -60,13 +60,14 @@ extern "C" int lap_batch_create(const lap_batch_job *jobs, int32_t n_jobs, void 
     std::vector<int32_t> h_col;
     for (int32_t j = 0; j < n_jobs; ++j) {
         const lap_batch_job &J = jobs[j];
-        if (J.n_samples < 1 || J.n_samples >= ((int64_t)1 << 56) || (J.flags & ~(uint32_t)LAP_KEEP_LCC)) {
+        if (J.n_samples < 1 || J.n_samples >= ((int64_t)1 << 56) || (J.flags & ~(uint32_t)(LAP_KEEP_LCC | LAP_DEGREE_ORDER))) {
             delete b;
             return fail(LAP_EINVAL, "job " + std::to_string(j) + ": bad n_samples or flags");
         }
         HostCSR csr;
         std::string err;
-        int rc = build_host_csr(J.n, J.n_edges, J.src, J.dst, (J.flags & LAP_KEEP_LCC) != 0, csr, err);
+        int rc = build_host_csr(J.n, J.n_edges, J.src, J.dst, (J.flags & LAP_KEEP_LCC) != 0, csr, err,
+                                (J.flags & LAP_DEGREE_ORDER) != 0);
         if (rc != LAP_OK) {
             delete b;
             return fail(rc, "job " + std::to_string(j) + ": " + err);

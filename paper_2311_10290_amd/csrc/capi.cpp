@@ -21,11 +21,12 @@ using namespace lap;
 extern "C" int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst,
                              uint32_t flags, void *hip_stream, lap_graph **out) {
     if (!out) return fail(LAP_EINVAL, "out is NULL");
-    if (flags & ~(uint32_t)LAP_KEEP_LCC) return fail(LAP_EINVAL, "unknown flag bits");
+    if (flags & ~(uint32_t)(LAP_KEEP_LCC | LAP_DEGREE_ORDER)) return fail(LAP_EINVAL, "unknown flag bits");
     lap_graph *g = new (std::nothrow) lap_graph();
     if (!g) return fail(LAP_ENOMEM, "host allocation failed");
     std::string err;
-    int rc = build_host_csr(n, n_edges, src, dst, (flags & LAP_KEEP_LCC) != 0, g->csr, err);
+    int rc = build_host_csr(n, n_edges, src, dst, (flags & LAP_KEEP_LCC) != 0, g->csr, err,
+                            (flags & LAP_DEGREE_ORDER) != 0);
     if (rc != LAP_OK) {
         delete g;
         return fail(rc, err);

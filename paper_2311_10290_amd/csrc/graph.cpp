@@ -6,8 +6,12 @@
 //   4. connected components by breadth-first search from the smallest
 //      unlabelled id;
 //   5. not connected: keep the largest component (ties: the one holding the
-//      smallest id) and renumber its nodes by ascending original id, or fail.
-// Neighbours come out sorted ascending.
+//      smallest id) and renumber its nodes by ascending original id, or fail;
+//   6. optionally number the kept nodes by decreasing degree instead, ties by
+//      increasing original id.  Hubs then share state lines and the rows of
+//      nodes of equal degree lie side by side, which is where the walkers
+//      start one after another.
+// Neighbours come out sorted ascending (in the final numbering).
 #include <stdint.h>
 
 #include <algorithm>
@@ -43,7 +47,7 @@ static void for_row_ranges(int64_t rows, const std::vector<int64_t> &rp, F f) {
 }
 
 int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst, bool keep_lcc,
-                   HostCSR &out, std::string &err) {
+                   HostCSR &out, std::string &err, bool degree_order) {
     if (n < 1 || n >= (int64_t)1 << 31) {
         err = "n must be in [1, 2^31)";
         return LAP_EINVAL;
@@ -168,21 +172,24 @@ int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t
     std::vector<int32_t> newid((size_t)n, -1);
     out.old_ids.clear();
     for (int64_t u = 0; u < n; ++u)
-        if (comp[u] == keep) {
-            newid[u] = (int32_t)out.old_ids.size();
-            out.old_ids.push_back((int32_t)u);
-        }
+        if (comp[u] == keep) out.old_ids.push_back((int32_t)u);
+    if (degree_order)
+        std::stable_sort(out.old_ids.begin(), out.old_ids.end(),
+                         [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+    for (size_t v = 0; v < out.old_ids.size(); ++v) newid[out.old_ids[v]] = (int32_t)v;
     const int64_t n2 = (int64_t)out.old_ids.size();
     out.n = n2;
     out.rp.assign((size_t)n2 + 1, 0);
     for (int64_t v = 0; v < n2; ++v) out.rp[v + 1] = out.rp[v] + deg[out.old_ids[v]];
     out.col.resize((size_t)out.rp[n2]);
-    // renumbering keeps the ascending order inside every row
+    // renumbering by ascending id keeps the order inside every row; by degree
+    // the rows are sorted again
     for_row_ranges(n2, out.rp, [&](int64_t lo, int64_t hi) {
         for (int64_t v = lo; v < hi; ++v) {
             const int64_t u = out.old_ids[v];
             int32_t *o = out.col.data() + out.rp[v];
             for (int64_t j = rp[u]; j < rp[u] + deg[u]; ++j) *o++ = newid[adj[(size_t)j]];
+            if (degree_order) std::sort(out.col.data() + out.rp[v], o);
         }
     });
     return LAP_OK;

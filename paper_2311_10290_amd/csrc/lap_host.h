@@ -19,8 +19,10 @@ struct HostCSR {
     std::vector<int32_t> old_ids;
 };
 
+// degree_order: number the kept nodes by decreasing degree, ties by
+// increasing original id (a relabelling of the same graph; old_ids maps back)
 int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst, bool keep_lcc,
-                   HostCSR &out, std::string &err);
+                   HostCSR &out, std::string &err, bool degree_order = false);
 
 // graphs whose column array has at least this many bytes also get arc records
 constexpr int64_t kArcsMinColBytes = (int64_t)64 << 20;

@@ -32,7 +32,8 @@ def small_cases():
     return out
 
 
-def both(n, s, d, keep_lcc=False):
+def both(n, s, d, keep_lcc=False, degree_order=False):
     """(oracle graph, HIP graph) built from the same edge list."""
     from paper_2311_10290_amd import Graph
-    return csr.build_csr(n, s, d, keep_lcc=keep_lcc), Graph(n, s, d, keep_lcc=keep_lcc)
+    return (csr.build_csr(n, s, d, keep_lcc=keep_lcc, degree_order=degree_order),
+            Graph(n, s, d, keep_lcc=keep_lcc, degree_order=degree_order))

@@ -2,7 +2,8 @@
 // tests/test_host_sanitizers.py under AddressSanitizer + UBSan and under
 // ThreadSanitizer.  Random multigraphs with self-loops, duplicate edges and
 // several components are built with and without keeping the largest
-// component, and compared with a plain sort-and-unique construction.  Two
+// component, and compared with a plain sort-and-unique construction; the
+// degree-ordered numbering is compared with the plain one.  Two
 // graphs are large enough (over 2^20 row entries) for every threaded pass.
 #include <algorithm>
 #include <cstdio>
@@ -73,6 +74,55 @@ int check(int64_t n, const std::vector<int32_t> &s, const std::vector<int32_t> &
     return bad;
 }
 
+// the same graph numbered by decreasing degree (ties by increasing original
+// id): the same kept nodes, the same edges, rows ascending
+int check_degree_order(int64_t n, const std::vector<int32_t> &s, const std::vector<int32_t> &d, bool keep) {
+    HostCSR a, b;
+    std::string err;
+    const int ra = build_host_csr(n, (int64_t)s.size(), s.data(), d.data(), keep, a, err);
+    const int rb = build_host_csr(n, (int64_t)s.size(), s.data(), d.data(), keep, b, err, true);
+    if (ra != rb) return 1;
+    if (ra != LAP_OK) return 0;
+    if (a.n != b.n || a.rp[a.n] != b.rp[b.n]) return 1;
+    const int64_t m = a.n;
+    // original id of every node of a
+    std::vector<int32_t> orig_a(m), orig_b(m);
+    for (int64_t u = 0; u < m; ++u) {
+        orig_a[u] = keep ? a.old_ids[u] : (int32_t)u;
+        orig_b[u] = b.old_ids[u];
+    }
+    std::vector<int32_t> sa = orig_a, sb = orig_b;
+    std::sort(sa.begin(), sa.end());
+    std::sort(sb.begin(), sb.end());
+    if (sa != sb) return 1;
+    std::vector<int32_t> a_of_orig(n, -1);
+    for (int64_t u = 0; u < m; ++u) a_of_orig[orig_a[u]] = (int32_t)u;
+    int bad = 0;
+    for (int64_t v = 0; v < m; ++v) {
+        const int64_t dv = b.rp[v + 1] - b.rp[v];
+        if (v > 0) {
+            const int64_t dp = b.rp[v] - b.rp[v - 1];
+            if (dp < dv || (dp == dv && orig_b[v - 1] >= orig_b[v])) ++bad;
+        }
+        const int32_t u = a_of_orig[orig_b[v]];
+        if (u < 0 || a.rp[u + 1] - a.rp[u] != dv) {
+            ++bad;
+            continue;
+        }
+        std::vector<int32_t> ra_row, rb_row;
+        for (int64_t j = a.rp[u]; j < a.rp[u + 1]; ++j) ra_row.push_back(orig_a[a.col[j]]);
+        for (int64_t j = b.rp[v]; j < b.rp[v + 1]; ++j) {
+            if (j > b.rp[v] && b.col[j - 1] >= b.col[j]) ++bad;
+            rb_row.push_back(orig_b[b.col[j]]);
+        }
+        std::sort(ra_row.begin(), ra_row.end());
+        std::sort(rb_row.begin(), rb_row.end());
+        if (ra_row != rb_row) ++bad;
+    }
+    if (bad) std::printf("n=%ld keep=%d degree order: %d mismatches\n", (long)n, (int)keep, bad);
+    return bad;
+}
+
 }  // namespace
 
 int main() {
@@ -90,6 +140,8 @@ int main() {
         }
         bad += check(n, s, d, false);
         bad += check(n, s, d, true);
+        bad += check_degree_order(n, s, d, true);
+        if (it % 4 == 0) bad += check_degree_order(n, s, d, false);
     }
     HostCSR g;
     std::string err;

@@ -38,6 +38,20 @@ def test_arc_form_bit_exact(rmat19, mode, group, pool):
     _same(got, exp, ["Y1", "y1", "next", "draws", "Y2", "len_uniform", "len_pi"])
 
 
+@pytest.mark.parametrize("mode,group", [(WAVE, 0), (GROUP, 8)])
+def test_arc_form_degree_ordered_graph(mode, group):
+    """The same graph numbered by decreasing degree (the layout of the large
+    workload): still bit-exact against the oracle on the same numbering."""
+    s, d = gg.rmat(19, 32, seed=5)
+    og, hg = both(1 << 19, s, d, keep_lcc=True, degree_order=True)
+    root = csr.landmark(og)
+    assert root == 0
+    log(f"arcs rmat19 degree order mode {mode} group {group}")
+    got = hg.sample_forests(40, 3, root, B=4, keep=[0, 39], y2=True, y2_pi=True, mode=mode, group=group)
+    exp = _oracle_counts(og, root, 40, 3, B=4, keep=[0, 39])
+    _same(got, exp, ["Y1", "y1", "next", "draws", "Y2", "len_uniform", "len_pi"])
+
+
 def test_arc_form_other_root_and_rotated_scan(rmat19):
     og, hg = rmat19
     root = int(np.argsort(og.deg)[-7])      # a hub that is not the landmark

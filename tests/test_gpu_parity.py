@@ -47,12 +47,13 @@ def test_csr_matches_oracle():
     d = rng.integers(0, 400_000, 1_200_000).astype(np.int32)
     cases.append(("sparse1.2M", 400_000, s, d))
     for name, n, s, d in cases + small_cases():
-        log(f"csr {name}")
-        og, hg = both(n, s, d, keep_lcc=True)
-        rp, col, old = hg.csr()
-        assert hg.n == og.n and hg.nnz == og.nnz
-        assert np.array_equal(rp, og.rp) and np.array_equal(col, og.col) and np.array_equal(old, og.old_ids)
-        assert hg.max_deg_node == csr.landmark(og)
+        for dord in (False, True):
+            log(f"csr {name} degree order {dord}")
+            og, hg = both(n, s, d, keep_lcc=True, degree_order=dord)
+            rp, col, old = hg.csr()
+            assert hg.n == og.n and hg.nnz == og.nnz
+            assert np.array_equal(rp, og.rp) and np.array_equal(col, og.col) and np.array_equal(old, og.old_ids)
+            assert hg.max_deg_node == csr.landmark(og)
 
 
 @pytest.mark.parametrize("mode", MODES)

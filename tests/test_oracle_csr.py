@@ -51,3 +51,39 @@ def test_lcc_tie_goes_to_smallest_id():
 def test_landmark_lowest_id_on_ties():
     g = csr.build_csr(4, [0, 1, 2, 3], [1, 2, 3, 0])
     assert csr.landmark(g) == 0
+
+
+@pytest.mark.parametrize("seed,keep", [(0, True), (1, True), (5, False)])
+def test_degree_order_is_a_relabelling(seed, keep):
+    """degree_order numbers the nodes by decreasing degree, ties by increasing
+    id, and is otherwise the same graph: networkx's edge set (in original
+    ids) and degrees are unchanged, rows stay ascending."""
+    if keep:
+        src, dst = gg.rmat(9, 6, seed=seed)
+        n = 512
+    else:
+        src, dst = gg.barabasi_albert(600, 3, seed)
+        n = 600
+    g = csr.build_csr(n, src, dst, keep_lcc=keep, degree_order=True)
+    nodes, rows = _nx_reference(n, src, dst, keep)
+    G = nx.Graph()
+    G.add_edges_from((int(a), int(b)) for a, b in zip(src, dst) if a != b)
+    assert sorted(g.old_ids.tolist()) == nodes
+    deg = np.diff(g.rp)
+    assert np.all(deg[:-1] >= deg[1:])
+    ties = deg[:-1] == deg[1:]
+    assert np.all(g.old_ids[:-1][ties] < g.old_ids[1:][ties])
+    for u in range(g.n):
+        row = g.col[g.rp[u]:g.rp[u + 1]]
+        assert np.all(np.diff(row) > 0)
+        assert sorted(g.old_ids[row].tolist()) == sorted(G.neighbors(int(g.old_ids[u])))
+    assert csr.landmark(g) == 0
+
+
+def test_degree_order_hand_case():
+    # a path 0-1-2 plus 2-3 and 2-4: node 2 (degree 3) first, then node 1
+    # (degree 2), then 0, 3, 4 (degree 1, by id)
+    g = csr.build_csr(5, [0, 1, 2, 2], [1, 2, 3, 4], degree_order=True)
+    assert g.old_ids.tolist() == [2, 1, 0, 3, 4]
+    assert g.rp.tolist() == [0, 3, 5, 6, 7, 8]
+    assert g.col.tolist() == [1, 3, 4, 0, 2, 1, 0, 0]
