@@ -47,8 +47,9 @@ typedef enum {
     LAP_ENOTCONN = -2,  /* graph not connected and LAP_KEEP_LCC not given (L_v singular) */
     LAP_ENOMEM = -3,    /* host or device allocation failed */
     LAP_EDEVICE = -4,   /* HIP runtime error, or no device */
-    LAP_ERANGE = -5     /* a count exceeded its field (e.g. more than 2^21 - 1 draws at one
+    LAP_ERANGE = -5,    /* a count exceeded its field (e.g. more than 2^21 - 1 draws at one
                            node in one sample) or a kernel passed its time limit */
+    LAP_ECANCELED = -6  /* a served query was cancelled (lap_server_cancel) */
 } lap_status;
 
 /* ------------------------------------------------------------------ graph */
@@ -467,7 +468,10 @@ typedef struct {
     int32_t kind;
     int32_t status;          /* LAP_OK, or the error that stopped the query */
     double value;            /* c(u), r(u,w) or kappa */
-    double se;               /* standard error of value over the query's walks / samples */
+    double se;               /* standard error of value over the query's own walks / samples.
+                                For closeness it is conditional on the cached global term
+                                Tr(L_v^{-1}) of lap_server_create (the only global term that
+                                enters c(u)), which it treats as exact. */
     double t_submit, t_start, t_done;   /* seconds since lap_server_create */
 } lap_query_result;
 
@@ -484,6 +488,8 @@ typedef struct {
     double timeout_s;        /* kernel time limit; 0 = 300 s */
     int32_t wilson_group;    /* wavefronts per Wilson sample in Wilson launches: 1 = wave form,
                                 2, 4 or 8 = workgroup form; 0 = 4 on graphs of >= 2^16 nodes, else 1 */
+    int32_t wilson_slots;    /* Wilson samples per Wilson launch at most (bounds the Wilson work
+                                that shares the device with walk tiles); 0 = waves */
 } lap_server_config;
 
 /* Compute the cached global terms (lap_sample_forests with qid
@@ -497,6 +503,13 @@ int lap_server_submit(lap_server *s, const lap_query *q);
 /* Retire, admit and launch (see above); with wait != 0 first block until a
  * running launch completes. */
 int lap_server_step(lap_server *s, int32_t wait);
+/* Cancel a queued or running query: a queued one leaves the queue at once; a
+ * running one issues no further work items, and its result region returns to
+ * the arena when the items already on the device have come back.  Either way
+ * lap_server_poll then returns its record with status LAP_ECANCELED and a NaN
+ * value.  Other queries' results are unchanged (they draw their own keyed
+ * streams).  LAP_EINVAL if no queued or running query has this id. */
+int lap_server_cancel(lap_server *s, int64_t qid);
 /* Move up to max completed results to out; *n_out receives their number. */
 int lap_server_poll(lap_server *s, lap_query_result *out, int32_t max, int32_t *n_out);
 /* Queries waiting for admission, admitted and not finished, launches running. */

@@ -7,7 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblap.so")
 
-LAP_OK, LAP_EINVAL, LAP_ENOTCONN, LAP_ENOMEM, LAP_EDEVICE, LAP_ERANGE = 0, -1, -2, -3, -4, -5
+LAP_OK, LAP_EINVAL, LAP_ENOTCONN, LAP_ENOMEM, LAP_EDEVICE, LAP_ERANGE, LAP_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 LAP_KEEP_LCC, LAP_DEGREE_ORDER = 1, 2
 LAP_WANT_Y1, LAP_WANT_Y2_UNIFORM, LAP_WANT_Y2_PI, LAP_WANT_PER_SAMPLE, LAP_OUT_DEVICE = 1, 2, 4, 8, 16
 LAP_MODE_AUTO, LAP_MODE_LANE, LAP_MODE_WAVE, LAP_MODE_GROUP = 0, 1, 2, 3
@@ -21,7 +21,8 @@ EXPORTS = [
     "lap_batch_create", "lap_batch_job_info", "lap_batch_run", "lap_batch_autotune", "lap_batch_result",
     "lap_batch_stats", "lap_batch_free", "lap_landmark_traces", "lap_spantree", "lap_spantree_estimate",
     "lap_loop_included", "lap_pair_paths", "lap_lv_rows", "lap_spantree_sample_bound",
-    "lap_server_create", "lap_server_submit", "lap_server_step", "lap_server_poll", "lap_server_pending",
+    "lap_server_create", "lap_server_submit", "lap_server_step", "lap_server_cancel", "lap_server_poll",
+    "lap_server_pending",
     "lap_server_globals", "lap_server_free",
 ]
 LAP_Q_CLOSENESS, LAP_Q_RESISTANCE, LAP_Q_KEMENY = 0, 1, 2
@@ -88,7 +89,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("root", ctypes.c_int32), ("stream", ctypes.c_uint32),
                 ("global_samples", ctypes.c_int64), ("arena_bytes", ctypes.c_int64), ("launches", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("items_per_launch", ctypes.c_int32), ("wilson_chunk", ctypes.c_int32),
-                ("timeout_s", ctypes.c_double), ("wilson_group", ctypes.c_int32)]
+                ("timeout_s", ctypes.c_double), ("wilson_group", ctypes.c_int32), ("wilson_slots", ctypes.c_int32)]
 
 
 def declare(lib):
@@ -127,6 +128,7 @@ def declare(lib):
         "lap_server_create": ([P, ctypes.POINTER(ServerConfig), P, P], i32),
         "lap_server_submit": ([P, ctypes.POINTER(Query)], i32),
         "lap_server_step": ([P, i32], i32),
+        "lap_server_cancel": ([P, i64], i32),
         "lap_server_poll": ([P, ctypes.POINTER(QueryResult), i32, P], i32),
         "lap_server_pending": ([P, P, P, P], i32),
         "lap_server_globals": ([P, P, P], i32),

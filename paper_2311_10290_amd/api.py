@@ -388,12 +388,12 @@ class Server:
 
     def __init__(self, graph: "Graph", seed=1, root=-1, stream_id=0, global_samples=0, arena_bytes=0,
                  launches=0, waves=0, items_per_launch=0, wilson_chunk=0, timeout_s=0.0, wilson_group=0,
-                 stream=None):
+                 wilson_slots=0, stream=None):
         cfg = C.ServerConfig(seed=int(seed), root=int(root), stream=int(stream_id), global_samples=int(global_samples),
                              arena_bytes=int(arena_bytes), launches=int(launches), waves=int(waves),
                              items_per_launch=int(items_per_launch), wilson_chunk=int(wilson_chunk),
                              timeout_s=float(timeout_s) if timeout_s else _default_timeout(),
-                             wilson_group=int(wilson_group))
+                             wilson_group=int(wilson_group), wilson_slots=int(wilson_slots))
         h = ctypes.c_void_p()
         _check(load_library().lap_server_create(graph._h, ctypes.byref(cfg), _stream(stream), ctypes.byref(h)))
         self._h = h
@@ -416,6 +416,9 @@ class Server:
 
     def step(self, wait=False):
         _check(load_library().lap_server_step(self._h, 1 if wait else 0))
+
+    def cancel(self, qid):
+        _check(load_library().lap_server_cancel(self._h, int(qid)))
 
     def poll(self, max_results=4096):
         buf = (C.QueryResult * max_results)()

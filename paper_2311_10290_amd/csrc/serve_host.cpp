@@ -20,6 +20,7 @@
 
 #include "lap_host.h"
 #include "lap_launch.h"
+#include "serve_arena.h"
 
 using namespace lap;
 
@@ -32,6 +33,7 @@ struct SQuery {
     int64_t next_wilson = 0, next_pi = 0, next_walk = 0;
     double t_submit = 0, t_start = -1;
     int status = LAP_OK;
+    bool cancelled = false;     // no new items; dropped once its issued items are back
 };
 
 struct SLaunch {
@@ -67,7 +69,7 @@ struct lap_server {
     std::map<int64_t, SQuery> active;     // by serial
     std::deque<SQuery> queue;
     std::vector<lap_query_result> done;
-    std::map<int64_t, int64_t> free_runs; // arena offset -> length (words)
+    WordArena words;                      // free runs of the result arena
     std::mutex mu;
     double tr_lv = 0, s_lv = 0;
     int64_t serial = 0;
@@ -93,32 +95,18 @@ struct lap_server {
 
 namespace {
 
-int64_t arena_alloc(lap_server *s, int64_t words) {
-    for (auto it = s->free_runs.begin(); it != s->free_runs.end(); ++it) {
-        if (it->second >= words) {
-            const int64_t off = it->first, len = it->second;
-            s->free_runs.erase(it);
-            if (len > words) s->free_runs[off + words] = len - words;
-            return off;
-        }
-    }
-    return -1;
-}
-
-void arena_free(lap_server *s, int64_t off, int64_t words) {
-    auto it = s->free_runs.emplace(off, words).first;
-    auto nx = std::next(it);
-    if (nx != s->free_runs.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        s->free_runs.erase(nx);
-    }
-    if (it != s->free_runs.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-            pv->second += it->second;
-            s->free_runs.erase(it);
-        }
-    }
+// a result record for a query that ends without a value
+lap_query_result ended(const lap_server *s, const SQuery &Q, int status) {
+    lap_query_result r;
+    std::memset(&r, 0, sizeof r);
+    r.qid = Q.q.qid;
+    r.kind = Q.q.kind;
+    r.status = status;
+    r.value = r.se = NAN;
+    r.t_submit = Q.t_submit;
+    r.t_start = Q.t_start;
+    r.t_done = now_s(s->t0);
+    return r;
 }
 
 double degree(const lap_graph *g, int32_t u) { return (double)(g->csr.rp[u + 1] - g->csr.rp[u]); }
@@ -184,12 +172,19 @@ int retire(lap_server *s, SLaunch &L) {
     }
     L.busy = false;
     L.serials.clear();
-    // finalise every query whose items have all come back
+    // finalise every query whose items have all come back (a cancelled one:
+    // every item it had issued)
     std::vector<int64_t> fin;
     for (auto &kv : s->active)
-        if (kv.second.finished == kv.second.n_items) fin.push_back(kv.first);
+        if (kv.second.finished == (kv.second.cancelled ? kv.second.issued : kv.second.n_items)) fin.push_back(kv.first);
     for (int64_t sr : fin) {
         SQuery &Q = s->active[sr];
+        if (Q.cancelled) {
+            s->done.push_back(ended(s, Q, LAP_ECANCELED));
+            s->words.release(Q.off, Q.words);
+            s->active.erase(sr);
+            continue;
+        }
         lap_query_result r;
         std::memset(&r, 0, sizeof r);
         r.qid = Q.q.qid;
@@ -206,7 +201,7 @@ int retire(lap_server *s, SLaunch &L) {
         }
         r.t_done = now_s(s->t0);
         s->done.push_back(r);
-        arena_free(s, Q.off, Q.words);
+        s->words.release(Q.off, Q.words);
         s->active.erase(sr);
     }
     if (e.code != kErrNone) {
@@ -225,6 +220,7 @@ int retire(lap_server *s, SLaunch &L) {
 // next work item of a query for a launch of class cls (0: walk tiles, 1:
 // Wilson samples, 2: either), or false if it has none left of that class
 bool next_item(lap_server *s, SQuery &Q, ServeItem &it, int cls) {
+    if (Q.cancelled) return false;
     const int64_t b = Q.q.budget;
     std::memset(&it, 0, sizeof it);
     it.budget = b;
@@ -270,7 +266,8 @@ int launch(lap_server *s, int idx) {
         // Wilson launches: at most one sample per state slot, oldest query
         // first, so that a launch lasts about one sample and the samples of a
         // Kemeny query finish together in as few launches as possible
-        const int64_t cap = std::min<int64_t>(s->cfg.items_per_launch, s->cfg.waves);
+        const int64_t cap = std::min<int64_t>({(int64_t)s->cfg.items_per_launch, (int64_t)s->cfg.waves,
+                                               (int64_t)s->cfg.wilson_slots});
         for (auto &kv : s->active) {
             SQuery &Q = kv.second;
             while (cnt < cap && Q.issued < Q.n_items && next_item(s, Q, L.h_items[cnt], cls)) {
@@ -345,7 +342,7 @@ extern "C" int lap_server_create(lap_graph *g, const lap_server_config *cfg, voi
     if (cfg) s->cfg = *cfg;
     lap_server_config &c = s->cfg;
     if (c.root < -1 || c.root >= s->n || c.global_samples < 0 || c.arena_bytes < 0 || c.launches < 0 ||
-        c.waves < 0 || c.items_per_launch < 0 || c.wilson_chunk < 0 ||
+        c.waves < 0 || c.items_per_launch < 0 || c.wilson_chunk < 0 || c.wilson_slots < 0 ||
         (c.wilson_group != 0 && c.wilson_group != 1 && c.wilson_group != 2 && c.wilson_group != 4 &&
          c.wilson_group != 8)) {
         delete s;
@@ -360,6 +357,7 @@ extern "C" int lap_server_create(lap_graph *g, const lap_server_config *cfg, voi
     if (c.wilson_chunk == 0) c.wilson_chunk = 1;
     if (c.timeout_s <= 0) c.timeout_s = 300.0;
     if (c.wilson_group == 0) c.wilson_group = s->n >= (1 << 16) ? 4 : 1;
+    if (c.wilson_slots == 0 || c.wilson_slots > c.waves) c.wilson_slots = c.waves;
     s->k1 = ((uint64_t)c.stream << 32) | (uint64_t)(uint32_t)c.root;
     s->deadline = (uint64_t)(c.timeout_s * g->clock_khz * 1000.0);
     // cached global terms: Tr(L_v^{-1}) and 1^T L_v^{-1} 1 from one Wilson +
@@ -409,7 +407,7 @@ extern "C" int lap_server_create(lap_graph *g, const lap_server_config *cfg, voi
         delete s;
         return fail(LAP_EDEVICE, "cannot clear serving memory");
     }
-    s->free_runs[0] = words;
+    s->words.reset(words);
     s->launches.resize((size_t)c.launches);
     for (auto &L : s->launches) {
         if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess ||
@@ -474,7 +472,7 @@ extern "C" int lap_server_step(lap_server *s, int32_t wait) {
     // 2. admit queued queries while their result regions fit in the arena
     while (!s->queue.empty()) {
         SQuery &Q = s->queue.front();
-        const int64_t off = arena_alloc(s, Q.words);
+        const int64_t off = s->words.alloc(Q.words);
         if (off < 0) break;
         Q.off = off;
         s->active[s->serial++] = Q;
@@ -487,6 +485,30 @@ extern "C" int lap_server_step(lap_server *s, int32_t wait) {
             if (r2 != LAP_OK) return r2;
         }
     return rc;
+}
+
+extern "C" int lap_server_cancel(lap_server *s, int64_t qid) {
+    if (!s) return fail(LAP_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+        if (it->q.qid == qid) {
+            s->done.push_back(ended(s, *it, LAP_ECANCELED));
+            s->queue.erase(it);
+            return LAP_OK;
+        }
+    for (auto it = s->active.begin(); it != s->active.end(); ++it) {
+        SQuery &Q = it->second;
+        if (Q.q.qid != qid || Q.cancelled) continue;
+        Q.cancelled = true;
+        if (Q.finished == Q.issued) {
+            // nothing of it on the device: its arena region is free at once
+            s->done.push_back(ended(s, Q, LAP_ECANCELED));
+            s->words.release(Q.off, Q.words);
+            s->active.erase(it);
+        }
+        return LAP_OK;
+    }
+    return fail(LAP_EINVAL, "no queued or running query with id " + std::to_string(qid));
 }
 
 extern "C" int lap_server_poll(lap_server *s, lap_query_result *out, int32_t max, int32_t *n_out) {

@@ -117,6 +117,43 @@ def test_admission_by_result_memory():
     srv.close()
 
 
+def test_cancel_queued_and_running_queries():
+    """Cancelling: a queued query leaves at once, a running one stops issuing
+    work and gives its arena region back when its items on the device are
+    done; both come back with status LAP_ECANCELED.  Every other query's
+    result equals its result in a run without cancellations, and the whole
+    arena is free again afterwards."""
+    from paper_2311_10290_amd import LapError, Server
+    og, hg, root, qs = _setup()
+    ref, _ = _run(hg, qs)
+    words = sum((4 if q["kind"] == 1 else 2) * q["budget"] for q in qs)
+    srv = Server(hg, seed=SEED, global_samples=512, launches=2, items_per_launch=2, waves=3,
+                 arena_bytes=8 * words, wilson_slots=2)
+    for q in qs:
+        srv.submit(q["qid"], q["kind"], q["budget"], q["u"], q["w"])
+    srv.cancel(qs[-1]["qid"])                 # still queued
+    srv.step()
+    running = next(q for q in qs if q["budget"] > 100)
+    srv.cancel(running["qid"])                # admitted, items on the device
+    with pytest.raises(LapError) as ei:
+        srv.cancel(123456789)
+    assert ei.value.code == -1
+    res = {r["qid"]: r for r in srv.run_all(timeout_s=120)}
+    assert sorted(res) == sorted(q["qid"] for q in qs)
+    for q in qs:
+        r = res[q["qid"]]
+        if q["qid"] in (qs[-1]["qid"], running["qid"]):
+            assert r["status"] == -6 and np.isnan(r["value"]), q
+        else:
+            assert r["status"] == 0 and r["value"] == ref[q["qid"]]["value"], q
+    assert srv.pending() == dict(queued=0, active=0, inflight=0)
+    # the arena is whole again: one query as large as all of them together runs
+    srv.submit(777, 0, words // 2, u=3)
+    big = srv.run_all(timeout_s=120)
+    assert len(big) == 1 and big[0]["status"] == 0
+    srv.close()
+
+
 def _random_graph(rng, case):
     kind = case % 3
     if kind == 0:
@@ -159,6 +196,7 @@ def test_random_server_configs_match_oracle(case):
                items_per_launch=[0, 1, 2, 7, 50][int(rng.integers(0, 5))],
                wilson_chunk=[0, 1, 3][int(rng.integers(0, 3))], wilson_group=[0, 1, 2, 4, 8][int(rng.integers(0, 5))],
                arena_bytes=0 if rng.random() < 0.5 else 8 * words * int(rng.integers(1, 4)))
+    cfg["wilson_slots"] = [0, 1, 2, 5][case % 4]
     G = int(rng.integers(16, 257))
     log(f"random serve case {case}: n={og.n} root={root} queries={len(qs)} cfg={cfg}")
     srv = Server(hg, seed=SEED, root=root, global_samples=G, **cfg)

@@ -55,3 +55,15 @@ def test_oracle_sampler_under_address_and_ub_sanitizers(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
+
+
+@pytest.mark.skipif(not os.path.exists("/usr/bin/g++"), reason="g++ not found")
+def test_serving_arena_policy(tmp_path):
+    """The serving result arena's first-fit policy (host code, no device)
+    under AddressSanitizer and UBSan, against a per-word occupancy map."""
+    exe = str(tmp_path / "arena_check")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-I", CSRC, os.path.join(HERE, "host", "arena_check.cpp"),
+                           "-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
