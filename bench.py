@@ -675,13 +675,17 @@ def bench_landmark(lap, gg):
     return res
 
 
-def bench_kc_families(lap, gg, n, er_omega):
+def bench_kc_families(lap, gg, n, er_omega, loop_omega=256):
     """Kemeny's constant of synthetic families (the paper's Sec. 6 study on
     BA, ER and hyperbolic graphs): BA with m = 2..6; ER with average degree
     200..1000 (p = 2..10 x 1e-4 at 1e6 nodes); hyperbolic with gamma =
-    2.2..3.0 and average degree 10 (largest component); 256 samples each,
-    er_omega for the ER graphs (their stationary-start walk lengths vary
-    most), all 15 graphs in one batched launch."""
+    2.2..3.0 and average degree 10 (largest component).  All 15 graphs in one
+    batched launch: 256 samples each, er_omega for the ER graphs (their
+    stationary-start walk lengths vary most).  Beside it, per graph, the same
+    Kemeny estimate with the stationary-start lengths taken from the
+    loop-included paths of the same Wilson samples (Sec. 3.4), loop_omega
+    samples: the two terms are then strongly correlated and the standard
+    error falls."""
     import torch
     t0 = time.perf_counter()
     jobs, labels = [], []
@@ -700,7 +704,6 @@ def bench_kc_families(lap, gg, n, er_omega):
     log(f"kc families: {len(jobs)} graphs generated in {time.perf_counter() - t0:.1f} s "
         f"({sum(len(j['src']) for j in jobs) / 1e6:.0f} M edges)")
     b = lap.Batch(jobs)
-    del jobs
     gen_s = time.perf_counter() - t0
     log(f"kc families: batch built in {gen_s:.1f} s")
     tuning = lap.Batch.tuning()
@@ -720,9 +723,22 @@ def bench_kc_families(lap, gg, n, er_omega):
                      "rel_se": float(r["kemeny_se"][0] / r["kemeny"][0])})
     st = b.stats()
     b.close()
-    return {"workload": f"15 synthetic graphs, n={n}, 256 samples each ({er_omega} for ER), one batched launch",
+    loop_s = 0.0
+    for j, job in enumerate(jobs):
+        g = lap.Graph(job["n"], job["src"], job["dst"], keep_lcc=True)
+        tt = time.perf_counter()
+        y1 = g.sample_forests(loop_omega, 1, -1, y1=False, per_sample=True)["y1"]
+        ln = g.loop_included(loop_omega, 1, 2, -1)["len"]
+        loop_s += time.perf_counter() - tt
+        z = (y1 - ln).astype(np.float64)
+        k, se = float(z.mean()), float(z.std(ddof=1) / math.sqrt(loop_omega))
+        rows[j].update({"kemeny_loop": k, "kemeny_loop_se": se, "loop_rel_se": se / k, "loop_omega": loop_omega,
+                        "corr_y1_len_loop": float(np.corrcoef(y1, ln)[0, 1])})
+        g.close()
+    return {"workload": f"15 synthetic graphs, n={n}, 256 samples each ({er_omega} for ER), one batched launch; "
+                        f"loop-included estimate with {loop_omega} samples per graph",
             "s": dt, "prepare_s": gen_s, "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) / dt,
-            "graphs": rows}
+            "loop_estimate_s": loop_s, "graphs": rows}
 
 
 def main():
@@ -736,7 +752,7 @@ def main():
     ap.add_argument("--skip", default="", help="comma-separated sections to leave out")
     ap.add_argument("--batch-jobs", type=int, default=512)
     ap.add_argument("--kc-n", type=int, default=100_000)
-    ap.add_argument("--kc-er-omega", type=int, default=4096)
+    ap.add_argument("--kc-er-omega", type=int, default=16384)
     ap.add_argument("--serve-queries", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
