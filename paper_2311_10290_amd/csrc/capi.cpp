@@ -70,9 +70,7 @@ extern "C" int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, con
         return LAP_OK;
     };
     // arcs: the target of every column entry with the target's adjacency
-    // record, so a walk step is one dependent load; only for column arrays
-    // beyond what the caches hold (smaller graphs keep col and nbr cached,
-    // and the 4x larger records would only add misses)
+    // record, so a walk step or a Wilson draw is one dependent load
     std::vector<uint64_t> arcs;
     if (4 * nnz >= kArcsMinColBytes) {
         arcs.resize(2 * (size_t)nnz);
@@ -300,7 +298,7 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         wp.n_slots = r.slots;   // lanes or waves taking part; <= allocated slots
         wp.nbr = g->nbr.as<uint64_t>();
         wp.col = g->col.as<int32_t>();
-        wp.arcs = (const ulonglong2 *)g->arcs.ptr;   // null below kArcsMinColBytes
+        wp.arcs = (const ulonglong2 *)g->arcs.ptr;   // null when the graph has no arc records
         wp.root = r.root;
         wp.k0 = a->seed;
         wp.k1 = k1;

@@ -24,8 +24,10 @@ struct HostCSR {
 int build_host_csr(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst, bool keep_lcc,
                    HostCSR &out, std::string &err, bool degree_order = false);
 
-// graphs whose column array has at least this many bytes also get arc records
-constexpr int64_t kArcsMinColBytes = (int64_t)64 << 20;
+// graphs whose column array has at least this many bytes also get arc
+// records: every graph (with the Wilson samplers' arc form and degree
+// numbering the records pay even where columns and rows stay in cache)
+constexpr int64_t kArcsMinColBytes = 0;
 
 // BFS tree of the CSR from root, neighbours in ascending order: par[u] is u's
 // parent, -1 at the root.  Returns the number of nodes reached.

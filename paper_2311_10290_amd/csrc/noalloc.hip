@@ -163,7 +163,7 @@ extern "C" int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a
         wp.n_slots = slots;
         wp.nbr = g->nbr.as<uint64_t>();
         wp.col = g->col.as<int32_t>();
-        wp.arcs = (const ulonglong2 *)g->arcs.ptr;   // null below kArcsMinColBytes
+        wp.arcs = (const ulonglong2 *)g->arcs.ptr;   // null when the graph has no arc records
         wp.root = r.root;
         wp.k0 = a->seed;
         wp.k1 = k1;
