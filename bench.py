@@ -44,8 +44,10 @@ KERNEL_SOURCES = ["paper_2311_10290_amd/csrc/" + f for f in
 TRAFFIC = {
     "large": dict(file="profiles/traffic_wilson_group_rmat22.json", kernel="wilson_group_kernel<8, true>",
                   workload="R-MAT scale 22 LCC numbered by decreasing degree, omega=512, one launch"),
-    "mid": dict(file="profiles/traffic_wilson_wave_ba100k.json", kernel="wilson_wave_kernel<false>",
+    "mid": dict(file="profiles/traffic_wilson_wave_ba100k.json", kernel="wilson_wave_kernel<true>",
                 workload="Barabasi-Albert n=100000 m=5 numbered by decreasing degree, omega=4096, one launch"),
+    "small": dict(file="profiles/traffic_wilson_wave_er256.json", kernel="wilson_wave_kernel<true>",
+                  workload="ER(256, 0.05), omega=2^14, one launch"),
 }
 SECTIONS = ("large", "small", "mid", "gather", "spantree", "loop_paths", "pairs", "landmark", "kc_families",
             "batched", "serving")
@@ -98,8 +100,11 @@ def write_traffic(pmc_dir, which):
     fetch runs with TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum, write
     runs with TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum (the inputs of FETCH_SIZE
     and WRITE_SIZE), plus <which>_fetch/bench.json (the run's JSON line, for
-    the draws per launch).  Each byte count is scaled by the copy's bytes over
-    what the same counters read for the copy."""
+    the draws per launch), and optionally <which>_tcc/ with TCC_HIT_sum
+    TCC_MISS_sum TCC_REQ_sum TCP_TCC_READ_REQ_sum TCP_TCC_WRITE_REQ_sum (the
+    L1-to-L2 requests).  Each byte count is scaled by the copy's bytes over
+    what the same counters read for the copy; several launches of the kernel
+    in one run are averaged."""
     def fetch_bytes(c):
         rd, r32, bub = c["TCC_EA0_RDREQ_sum"], c["TCC_EA0_RDREQ_32B_sum"], c["TCC_BUBBLE_sum"]
         return bub * 128 + (rd - bub - r32) * 64 + r32 * 32
@@ -112,20 +117,28 @@ def write_traffic(pmc_dir, which):
     copy_bytes = 1 << 30
     cal_f = copy_bytes / fetch_bytes(_csv_counters(os.path.join(pmc_dir, "copy_fetch"), "copyBuffer")[0])
     cal_w = copy_bytes / write_bytes(_csv_counters(os.path.join(pmc_dir, "copy_write"), "copyBuffer")[0])
-    f = _csv_counters(os.path.join(pmc_dir, f"{which}_fetch"), spec["kernel"])
-    w = _csv_counters(os.path.join(pmc_dir, f"{which}_write"), spec["kernel"])
-    if len(f) != 1 or len(w) != 1:
-        raise SystemExit(f"expected one {spec['kernel']} dispatch per run, got {len(f)} and {len(w)}")
+    def mean(rows):
+        if not rows:
+            raise SystemExit(f"no {spec['kernel']} dispatch found")
+        return {k: sum(r[k] for r in rows) / len(rows) for k in rows[0]}
+
+    f = mean(_csv_counters(os.path.join(pmc_dir, f"{which}_fetch"), spec["kernel"]))
+    w = mean(_csv_counters(os.path.join(pmc_dir, f"{which}_write"), spec["kernel"]))
     with open(os.path.join(pmc_dir, f"{which}_fetch", "bench.json")) as fh:
         b = json.loads(fh.read().strip().splitlines()[-1])
-    draws = b["wilson_steps_per_step"] if which == "large" else b["mid"]["wilson_steps_per_step"]
+    draws = b["wilson_steps_per_step"] if which == "large" else b[which]["wilson_steps_per_step"]
     res = {"kernel": spec["kernel"], "workload": spec["workload"], "kernel_hash": kernel_hash(),
            "draws_per_launch": draws,
-           "fetch": {"counters": f[0], "raw_bytes": fetch_bytes(f[0]), "calibration": cal_f,
-                     "bytes": fetch_bytes(f[0]) * cal_f},
-           "write": {"counters": w[0], "raw_bytes": write_bytes(w[0]), "calibration": cal_w,
-                     "bytes": write_bytes(w[0]) * cal_w},
-           "read_requests_per_launch": f[0]["TCC_EA0_RDREQ_sum"]}
+           "fetch": {"counters": f, "raw_bytes": fetch_bytes(f), "calibration": cal_f,
+                     "bytes": fetch_bytes(f) * cal_f},
+           "write": {"counters": w, "raw_bytes": write_bytes(w), "calibration": cal_w,
+                     "bytes": write_bytes(w) * cal_w},
+           "read_requests_per_launch": f["TCC_EA0_RDREQ_sum"]}
+    tcc_dir = os.path.join(pmc_dir, f"{which}_tcc")
+    if os.path.isdir(tcc_dir):
+        t = mean(_csv_counters(tcc_dir, spec["kernel"]))
+        res["l2"] = {"counters": t, "l1_to_l2_read_requests_per_draw": t["TCP_TCC_READ_REQ_sum"] / draws,
+                     "l2_hit_rate": t["TCC_HIT_sum"] / max(t["TCC_REQ_sum"], 1.0)}
     res["bytes_per_launch"] = res["fetch"]["bytes"] + res["write"]["bytes"]
     res["bytes_per_draw"] = res["bytes_per_launch"] / draws
     res["read_requests_per_draw"] = res["read_requests_per_launch"] / draws
@@ -255,16 +268,17 @@ def rmat_graph(lap, gg, scale):
     return g, src, dst
 
 
-def bench_small(lap, gg, with_cpu, gather):
+def bench_small(lap, gg, steps, warmup, with_cpu, gather):
     """Small workload: ER(256, 0.05), graph seed 0, resampled until connected,
     root = max degree, omega = 2^14; accuracy against the dense FP64
-    pseudo-inverse at Philox seed 1 (CPU leg), GPU and CPU rates."""
+    pseudo-inverse at Philox seed 1 (CPU leg), GPU and CPU rates.  A step
+    takes about 2 ms, so four are timed per headline step."""
     n, omega = 256, 1 << 14
     src, dst, _ = gg.erdos_renyi_connected(n, 0.05, 0)
     g = lap.Graph(n, src, dst)
     root = g.max_deg_node
-    reps = 20
-    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, reps, 2)
+    reps = 4 * steps
+    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, reps, warmup)
     kms = kern[wk]["ms_avg"]
     res = {"workload": "ER(256, 0.05) seed 0 connected, root = max degree, omega = 2^14, Philox seed 1",
            "s_per_step": dt / reps, "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) * reps / dt,
@@ -273,12 +287,16 @@ def bench_small(lap, gg, with_cpu, gather):
            "wilson_steps_per_step": st["wilson_steps"],
            "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
     # the walk state of 4096 slots x 256 nodes (8 MB) sits in the caches: the
-    # reference is the L2-tier random-request rate of the sweep
-    if gather:
-        loads = 3.0 * st["wilson_steps"] / (kms * 1e-3)
-        res["cache_tier"] = {"state_bytes": 8 * n * min(omega, 4096), "loads_per_draw_assumed": 3,
-                             "loads_per_s": loads, "peak_4MiB": gather["tiers"]["4MiB"]["peak"],
-                             "frac_of_4MiB_peak": loads / gather["tiers"]["4MiB"]["peak"]}
+    # reference is the L2-tier random-request rate of the sweep, against the
+    # kernel's counted L1-to-L2 read requests
+    traffic = measured_traffic("small")
+    if gather and traffic and "l2" in traffic:
+        per = traffic["l2"]["l1_to_l2_read_requests_per_draw"]
+        rate = per * st["wilson_steps"] / (kms * 1e-3)
+        res["cache_tier"] = {"state_bytes": 8 * n * min(omega, 4096), "l1_to_l2_read_requests_per_draw": per,
+                             "l2_hit_rate": traffic["l2"]["l2_hit_rate"], "requests_per_s": rate,
+                             "peak_4MiB": gather["tiers"]["4MiB"]["peak"],
+                             "frac_of_4MiB_peak": rate / gather["tiers"]["4MiB"]["peak"]}
     if with_cpu:
         from oracle import csr as ocsr, dense, native
         og = ocsr.build_csr(n, src, dst)
@@ -354,7 +372,14 @@ def bench_gather(lap):
                         "peak": max(max(chase.values()), max(indep.values()))}
         log(f"gather {label}: chase peak {tiers[label]['chase_peak'] / 1e9:.1f} G/s, "
             f"independent peak {tiers[label]['independent_peak'] / 1e9:.1f} G/s")
-    return {"unit": "random 8-byte loads/s (one memory request each at the 4 GiB tier)", "tiers": tiers}
+    # the cache policy of the loads (plain, non-temporal, relaxed atomic at
+    # device and at system scope) at 4 GiB: chase with 2^19 lanes, independent
+    # with 2^18 lanes x 8 loads in flight
+    flavors = {name: {"chase": lap.bench_gather(4 << 30, 1 << 19, 1, 1, fl),
+                      "independent": lap.bench_gather(4 << 30, 1 << 18, 0, 8, fl)}
+               for fl, name in enumerate(("plain", "nontemporal", "atomic_device", "atomic_system"))}
+    return {"unit": "random 8-byte loads/s (one memory request each at the 4 GiB tier)", "tiers": tiers,
+            "flavors_4GiB": flavors}
 
 
 def bench_batch(lap, gg, n_jobs, with_cpu):
@@ -833,7 +858,7 @@ def main():
         del src, dst
     if "small" in only:
         log("small workload")
-        res["small"] = bench_small(lap, gg, with_cpu, gather)
+        res["small"] = bench_small(lap, gg, args.steps, args.warmup, with_cpu, gather)
     mid = None
     if only & {"mid", "spantree", "loop_paths", "pairs"}:
         log("mid workload")
