@@ -208,7 +208,7 @@ def _out_tensors(n):
     return out
 
 
-def timed_steps(lap, g, omega, root, steps, warmup, B=64):
+def timed_steps(lap, g, omega, root, steps, warmup, B=64, walks=0):
     """Run warmup + steps plain steps on torch's current stream; time the
     steps between two device synchronisations, with per-kernel HIP-event
     timing (on the streams the kernels run on) over the timed region."""
@@ -216,20 +216,20 @@ def timed_steps(lap, g, omega, root, steps, warmup, B=64):
     out = _out_tensors(g.n)
     stream = torch.cuda.current_stream()
     for i in range(warmup):
-        g.estimate(omega, SEED, root, B=B, out=out, stream=stream)
+        g.estimate(omega, SEED, root, B=B, out=out, stream=stream, walks=walks)
     torch.cuda.synchronize()
     lap.prof_reset()
     lap.prof_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        g.estimate(omega, SEED, root, B=B, out=out, stream=stream)
+        g.estimate(omega, SEED, root, B=B, out=out, stream=stream, walks=walks)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lap.prof_enable(False)
     st = g.last_stats()
     kern = {}
-    for name in ("wilson_group", "wilson_wave", "wilson_lane", "absorbed", "assemble"):
+    for name in ("wilson_group", "wilson_wave", "wilson_lane", "absorbed", "loop_included", "assemble"):
         ms, n = lap.prof_read(name)
         if n:
             kern[name] = {"ms_avg": ms / n, "launches": n}
@@ -312,6 +312,16 @@ def bench_small(lap, gg, steps, warmup, with_cpu, gather):
         c_gpu = out["closeness"].cpu().numpy()
         k_gpu = float(out["kemeny"].item())
         rel_c = np.abs(c_gpu - c_true) / c_true
+        # the same samples with loop-included paths in place of fresh walks
+        dtl, stl, kernl, _, outl = timed_steps(lap, g, omega, root, reps, warmup, walks=1)
+        c_loop = outl["closeness"].cpu().numpy()
+        k_loop = float(outl["kemeny"].item())
+        rel_l = np.abs(c_loop - c_true) / c_true
+        res["loop_included_estimator"] = {
+            "s_per_step": dtl / reps, "kernel_ms": {k: v["ms_avg"] for k, v in kernl.items()},
+            "kemeny_rel_err": abs(k_loop - k_true) / k_true,
+            "kemeny_z": (k_loop - k_true) / float(outl["kemeny_se"].item()),
+            "closeness_mean_rel_err": float(rel_l.mean()), "closeness_max_rel_err": float(rel_l.max())}
         res["accuracy_vs_dense_pinv"] = {
             "kemeny_rel_err": abs(k_gpu - k_true) / k_true, "kemeny_exact": k_true,
             "kemeny_z": (k_gpu - k_true) / float(out["kemeny_se"].item()),
@@ -848,6 +858,14 @@ def main():
         log(f"large: {res['ms_per_step']:.2f} ms per step, {res['value'] / 1e9:.2f} G walk steps/s, "
             f"Wilson {kms:.2f} ms")
         root = g.max_deg_node
+        # the same step with the walk counts from the loop-included paths of
+        # the same Wilson samples (Sec. 3.4): after the trees, not beside them
+        dtl, stl, kernl, _, outl = timed_steps(lap, g, omega, -1, 2, 1, walks=1)
+        res["large_loop_included"] = {
+            "s_per_step": dtl / 2, "kernel_ms": {k: v["ms_avg"] for k, v in kernl.items()},
+            "path_steps_per_step": stl["absorbed_steps"],
+            "kemeny": float(outl["kemeny"].item()), "kemeny_se": float(outl["kemeny_se"].item()),
+            "trace_Ldagger": float(outl["trace"].item())}
         g.close()
         if with_cpu:
             log("large: cpu baseline (oracle)")

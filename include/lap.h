@@ -124,7 +124,17 @@ typedef struct {
     int64_t schedule;      /* wave and workgroup forms: the start scan begins at node (schedule mod n)
                               and wraps; counts do not depend on it (a knob for schedule-randomised tests) */
     int32_t group;         /* workgroup form: wavefronts per sample (2, 4 or 8); 0 = automatic */
+    int32_t walks;         /* lap_estimate only: where the v-absorbed walk counts come from.
+                              LAP_WALKS_FRESH (0): fresh walks with their own draws (Alg. 2, Alg. 4).
+                              LAP_WALKS_LOOP (1): the loop-included paths of the same Wilson samples,
+                              started like the fresh walks (Sec. 3.4: each path has the law of a
+                              v-absorbed walk, so the estimates stay unbiased; sharing the samples'
+                              stacks correlates them with the draw counts and shrinks the variance
+                              of both estimators).  Samples then run in rounds of the state slots,
+                              each round followed by its paths. */
 } lap_sample_args;
+
+enum { LAP_WALKS_FRESH = 0, LAP_WALKS_LOOP = 1 };
 
 typedef struct {
     int64_t *y1;             /* [B][n] Wilson draws per node (sum over samples), or NULL */

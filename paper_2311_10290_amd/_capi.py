@@ -35,7 +35,7 @@ class SampleArgs(ctypes.Structure):
         ("stream", ctypes.c_uint32), ("qid", ctypes.c_uint64), ("want", ctypes.c_uint32),
         ("n_blocks", ctypes.c_int32), ("sample_begin", ctypes.c_int64), ("n_total", ctypes.c_int64),
         ("mode", ctypes.c_int32), ("pool", ctypes.c_int32), ("timeout_s", ctypes.c_double),
-        ("schedule", ctypes.c_int64), ("group", ctypes.c_int32),
+        ("schedule", ctypes.c_int64), ("group", ctypes.c_int32), ("walks", ctypes.c_int32),
     ]
 
 

@@ -124,12 +124,12 @@ class Graph:
         return rp, col, old
 
     def _args(self, omega, seed, root, want, B, sample_begin, n_total, mode, pool, stream_id, qid, timeout_s,
-              schedule=0, group=0):
+              schedule=0, group=0, walks=0):
         return C.SampleArgs(n_samples=int(omega), seed=int(seed), root=int(root), stream=int(stream_id),
                             qid=int(qid), want=int(want), n_blocks=int(B), sample_begin=int(sample_begin),
                             n_total=int(n_total), mode=int(mode), pool=int(pool),
                             timeout_s=float(timeout_s) if timeout_s else _default_timeout(),
-                            schedule=int(schedule), group=int(group))
+                            schedule=int(schedule), group=int(group), walks=int(walks))
 
     def sample_forests(self, omega, seed, root=-1, *, y1=True, y2=False, y2_pi=False, per_sample=True,
                        B=1, keep=(), sample_begin=0, n_total=0, mode=0, pool=0, stream_id=0, qid=0,
@@ -191,7 +191,7 @@ class Graph:
 
     def estimate(self, omega, seed, root=-1, *, diag=True, se=True, lv=False, closeness=True, kemeny=True,
                  derived=False, B=64, mode=0, pool=0, stream_id=0, qid=0, timeout_s=0.0, group=0, stream=None,
-                 out=None):
+                 out=None, walks=0):
         """FP64 estimates of lap_estimate.  With ``out`` (a dict of torch device
         tensors: diag, diag_se, lv_diag, closeness [n]; trace, kemeny,
         kemeny_se [1]) results are written there on the device."""
@@ -199,7 +199,7 @@ class Graph:
         dev = out is not None
         want = C.LAP_OUT_DEVICE if dev else 0
         a = self._args(omega, seed, root, want, B if se else 1, 0, 0, mode, pool, stream_id, qid, timeout_s,
-                       group=group)
+                       group=group, walks=walks)
         if dev:
             res = out
         else:

@@ -142,6 +142,7 @@ int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, c
     if (a->group != 0 && a->group != 2 && a->group != 4 && a->group != 8)
         return fail(LAP_EINVAL, "group must be 0, 2, 4 or 8");
     if (a->pool < 0) return fail(LAP_EINVAL, "pool must be >= 0");
+    if (a->walks != LAP_WALKS_FRESH && a->walks != LAP_WALKS_LOOP) return fail(LAP_EINVAL, "unknown walks");
     if (a->want & ~(uint32_t)(LAP_WANT_Y1 | LAP_WANT_Y2_UNIFORM | LAP_WANT_Y2_PI | LAP_WANT_PER_SAMPLE |
                               LAP_OUT_DEVICE))
         return fail(LAP_EINVAL, "unknown want bits");
@@ -228,8 +229,16 @@ struct RunOut {
     int32_t *keep_next = nullptr, *keep_draws = nullptr;
 };
 
+// Wilson samples of r (and, with loop_walks false, the requested absorbed
+// walks beside them on the auxiliary stream).  With loop_walks true the
+// walk counts come from the loop-included paths of the same samples instead:
+// every sample of a round keeps its own state slot (one wave, workgroup or
+// lane per sample; as many as 48 GiB of state and path counters hold), and
+// each round's trees are followed by one path per sample for each requested
+// start law.
 int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int64_t n_keep,
-                 const int64_t *keep_idx, bool want_y1, bool want_y1s, RunOut &o, hipStream_t s, Timer &tm) {
+                 const int64_t *keep_idx, bool want_y1, bool want_y1s, RunOut &o, hipStream_t s, Timer &tm,
+                 bool loop_walks = false) {
     const int64_t n = g->csr.n;
     const size_t bn = sizeof(uint64_t) * (size_t)r.B * n;
     if (g->err.ensure(sizeof(DevErr)) || g->stats.ensure(sizeof(uint64_t) * kNumStats))
@@ -252,7 +261,7 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
     const uint64_t k1 = ((uint64_t)a->stream << 32) | (uint64_t)(uint32_t)r.root;
 
     // absorbed walks run on the auxiliary stream, overlapping the Wilson kernel
-    const bool any_walks = r.y2u || r.y2p;
+    const bool any_walks = (r.y2u || r.y2p) && !loop_walks;
     if (any_walks) {
         if (!g->aux) {
             HIP_TRY(hipStreamCreateWithFlags(&g->aux, hipStreamNonBlocking));
@@ -288,14 +297,23 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         tm.end(g->aux);
         HIP_TRY(hipEventRecord(g->ev_join, g->aux));
     }
-    if (r.wilson) {
-        int rc = ensure_state(g, r.slots, s);
+    const bool loop = loop_walks && r.wilson && (r.y2u || r.y2p);
+    int64_t round = r.omega;   // samples per Wilson launch
+    if (loop) {
+        round = std::max<int64_t>(1, std::min<int64_t>(r.omega, ((int64_t)48 << 30) / (12 * std::max<int64_t>(n, 1))));
+        if (g->loop_cnt.ensure(sizeof(int32_t) * (size_t)round * n + 8))
+            return fail(LAP_ENOMEM, "cannot allocate loop-included path workspace");
+    }
+    for (int64_t done = 0; r.wilson && done < r.omega; done += round) {
+        const int64_t rows = std::min(round, r.omega - done);
+        const int64_t slots = loop ? rows : std::min(r.slots, rows);
+        int rc = ensure_state(g, slots, s);
         if (rc != LAP_OK) return rc;
         WilsonParams wp;
         std::memset(&wp, 0, sizeof wp);
         wp.n = n;
         wp.nnz = g->csr.rp[n];
-        wp.n_slots = r.slots;   // lanes or waves taking part; <= allocated slots
+        wp.n_slots = slots;   // lanes, waves or workgroups taking part; <= allocated slots
         wp.nbr = g->nbr.as<uint64_t>();
         wp.col = g->col.as<int32_t>();
         wp.arcs = (const ulonglong2 *)g->arcs.ptr;   // null when the graph has no arc records
@@ -303,14 +321,14 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         wp.k0 = a->seed;
         wp.k1 = k1;
         wp.qid = a->qid;
-        wp.sample_begin = r.begin;
-        wp.n_samples = r.omega;
+        wp.sample_begin = r.begin + done;
+        wp.n_samples = rows;
         wp.n_total = r.total;
         wp.n_blocks = r.B;
         wp.state = g->state.as<uint64_t>();
         wp.slot_epoch = g->epoch.as<uint32_t>();
         wp.y1 = want_y1 ? g->y1.as<unsigned long long>() : nullptr;
-        wp.y1_per_sample = g->y1s.as<int64_t>();
+        wp.y1_per_sample = g->y1s.as<int64_t>() + done;
         wp.n_keep = (int32_t)n_keep;
         for (int64_t q = 0; q < n_keep; ++q) wp.keep_idx[q] = keep_idx[q];
         wp.next_out = n_keep ? g->keep_next.as<int32_t>() : nullptr;
@@ -321,15 +339,46 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         wp.scan_offset = n > 0 ? ((a->schedule % n) + n) % n : 0;
         if (r.mode == LAP_MODE_LANE) {
             tm.begin("wilson_lane", s);
-            HIP_TRY(launch_wilson_lane(wp, r.slots, s));
+            HIP_TRY(launch_wilson_lane(wp, wp.n_slots, s));
         } else if (r.mode == LAP_MODE_GROUP) {
             tm.begin("wilson_group", s);
-            HIP_TRY(launch_wilson_group(wp, r.slots, r.group, s));
+            HIP_TRY(launch_wilson_group(wp, wp.n_slots, r.group, s));
         } else {
             tm.begin("wilson_wave", s);
-            HIP_TRY(launch_wilson_wave(wp, r.slots, s));
+            HIP_TRY(launch_wilson_wave(wp, wp.n_slots, s));
         }
         tm.end(s);
+        for (int kind = 1; loop && kind <= 2; ++kind) {
+            // one loop-included path per sample of the round, through its tree
+            if ((kind == 1 && !r.y2u) || (kind == 2 && !r.y2p)) continue;
+            HIP_TRY(launch_fill_u64(g->loop_cnt.as<uint64_t>(), 0ull, (rows * n + 1) / 2, s));
+            LoopParams lp;
+            std::memset(&lp, 0, sizeof lp);
+            lp.n = n;
+            lp.nnz = g->csr.rp[n];
+            lp.nbr = g->nbr.as<uint64_t>();
+            lp.col = g->col.as<int32_t>();
+            lp.root = r.root;
+            lp.k0 = a->seed;
+            lp.k1 = k1;
+            lp.qid = a->qid;
+            lp.tag = (uint32_t)kind;
+            lp.state = g->state.as<uint64_t>();
+            lp.slot_epoch = g->epoch.as<uint32_t>();
+            lp.cnt = g->loop_cnt.as<int32_t>();
+            lp.n_paths = rows;
+            lp.sample_begin = r.begin + done;
+            lp.n_total = r.total;
+            lp.n_blocks = r.B;
+            lp.y2 = kind == 1 ? g->y2.as<unsigned long long>() : nullptr;
+            lp.len_out = (kind == 1 ? g->len_u.as<int64_t>() : g->len_p.as<int64_t>()) + done;
+            lp.stats = g->stats.as<unsigned long long>();
+            lp.err = g->err.as<DevErr>();
+            lp.deadline = deadline;
+            tm.begin("loop_included", s);
+            HIP_TRY(launch_loop_included(lp, s));
+            tm.end(s);
+        }
     }
     (void)want_y1s;
     if (any_walks) HIP_TRY(hipStreamWaitEvent(s, g->ev_join, 0));
@@ -435,7 +484,7 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
     const int64_t n = g->csr.n;
     Timer tm;
     RunOut o;
-    rc = run_sampling(g, r, a, 0, nullptr, want_diag, true, o, s, tm);
+    rc = run_sampling(g, r, a, 0, nullptr, want_diag, true, o, s, tm, a->walks == LAP_WALKS_LOOP);
     if (rc != LAP_OK) return rc;
     // FP64 assembly on the device into handle-owned buffers
     const int32_t parts = (int32_t)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 1023) / 1024));

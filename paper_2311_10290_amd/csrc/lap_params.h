@@ -107,6 +107,7 @@ struct LoopParams {
     int32_t n_blocks;
     unsigned long long *y2;        // [B][n] or null
     int64_t *len_out;              // [n_paths] of this launch, or null
+    unsigned long long *stats;     // path steps are added to the absorbed-step count, or null
     DevErr *err;
     uint64_t deadline;
 };

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(64) void loop_included_kernel(LoopParams p) {
         }
     }
     if (p.len_out) p.len_out[slot] = len;
+    if (p.stats) atomicAdd(&p.stats[kStatAbsorbed], (unsigned long long)len);
 }
 
 hipError_t launch_loop_included(const LoopParams &p, hipStream_t s) {

@@ -175,6 +175,52 @@ def test_estimates_match_oracle_assembly_and_dense_truth():
     assert abs(est["kemeny"][0] - dense.kemeny_spectral(og)) < 3 * est["kemeny_se"][0]
 
 
+@pytest.mark.parametrize("mode,group,pool", [(0, 0, 0), (2, 0, 7), (3, 4, 0), (1, 0, 300)])
+def test_loop_included_estimates_match_oracle(mode, group, pool):
+    """lap_estimate with the walk counts from the loop-included paths of the
+    same Wilson samples (LAP_WALKS_LOOP): the samples run in rounds of the
+    state slots (several rounds here), and every output equals the oracle's
+    assembly of its Wilson counts and loop-included paths; at seed 1 the
+    estimates meet the 1e-2 relative target against the dense pseudo-inverse."""
+    n, s, d = er256_edges()
+    og, hg = both(n, s, d)
+    root = csr.landmark(og)
+    omega, B = 1 << 14, 64
+    log(f"loop estimate er256 mode {mode} group {group} pool {pool}")
+    est = hg.estimate(omega, 1, root, B=B, walks=1, mode=mode, group=group, pool=pool)
+    w = native.wilson(og, root, omega, 1, B=B)
+    l1 = native.loop_included(og, root, omega, 1, 1, B=B)
+    l2 = native.loop_included(og, root, omega, 1, 2)
+    diag, se = estimators.diag_ldagger_blocks(w["Y1"], l1["Y2"], omega, og.deg)
+    c, tr = estimators.closeness(diag)
+    k, kse = estimators.kemeny(w["y1"], l2["len"])
+    np.testing.assert_allclose(est["diag"], diag, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(est["diag_se"], se, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(est["closeness"], c, rtol=1e-12)
+    np.testing.assert_allclose(est["trace"][0], tr, rtol=1e-12)
+    np.testing.assert_allclose(est["kemeny"][0], k, rtol=1e-12)
+    np.testing.assert_allclose(est["kemeny_se"][0], kse, rtol=1e-9)
+    Ld = dense.pinv_eigh(dense.laplacian(og))
+    c_true = dense.closeness(Ld)
+    assert abs(est["kemeny"][0] / dense.kemeny_spectral(og) - 1) < 1e-2
+    assert np.max(np.abs(est["closeness"] - c_true) / c_true) < 1e-2
+
+
+def test_loop_included_estimates_on_small_graphs():
+    for name, n, s, d in small_cases():
+        og, hg = both(n, s, d)
+        root = csr.landmark(og)
+        log(f"loop estimate {name}")
+        est = hg.estimate(300, 4, root, B=4, walks=1, pool=7)
+        w = native.wilson(og, root, 300, 4, B=4)
+        l1 = native.loop_included(og, root, 300, 4, 1, B=4)
+        l2 = native.loop_included(og, root, 300, 4, 2)
+        diag, _ = estimators.diag_ldagger_blocks(w["Y1"], l1["Y2"], 300, og.deg)
+        k, _ = estimators.kemeny(w["y1"], l2["len"])
+        np.testing.assert_allclose(est["diag"], diag, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(est["kemeny"][0], k, rtol=1e-12, atol=1e-12)
+
+
 def test_derived_outputs_match_oracle():
     n, s, d = er256_edges()
     og, hg = both(n, s, d)

@@ -77,3 +77,47 @@ def test_er256_relative_error_target_over_seeds():
         ks.append(abs(k - k_true) / k_true)
     assert np.median(cs) < 1e-2
     assert np.median(ks) < 1e-2
+
+
+def _er256_loop_run(seed, omega=1 << 14, B=64):
+    """The same Wilson samples, with the absorbed-walk counts taken from
+    their loop-included paths (Sec. 3.4) instead of fresh walks."""
+    g = er256()
+    v = csr.landmark(g)
+    w = native.wilson(g, v, omega, seed, B=B)
+    l1 = native.loop_included(g, v, omega, seed, 1, B=B)
+    l2 = native.loop_included(g, v, omega, seed, 2)
+    diag, se = estimators.diag_ldagger_blocks(w["Y1"], l1["Y2"], omega, g.deg)
+    k, kse = estimators.kemeny(w["y1"], l2["len"])
+    return g, diag, se, k, kse
+
+
+def test_er256_loop_included_estimates_within_standard_errors():
+    g, diag, se, k, kse = _er256_loop_run(1)
+    Ld = dense.pinv_eigh(dense.laplacian(g))
+    z = (diag - np.diag(Ld)) / se
+    assert np.abs(z).max() < 4.6
+    assert (np.abs(z) < 3).mean() >= 0.97
+    assert abs(k - dense.kemeny_spectral(g)) < 3 * kse
+
+
+def test_er256_relative_error_target_at_seed_1():
+    """The 1e-2 relative target on the small ER workload at the configured
+    Philox seed 1.  The fresh-walk estimator misses it there (a ~2-sigma run:
+    kappa 1.1%, mean closeness 1.2%); the loop-included estimator on the same
+    2^14 Wilson samples meets it for kappa, the mean and the maximum closeness
+    error, because its walk counts share the samples' stacks and its errors
+    largely cancel."""
+    g = er256()
+    Ld = dense.pinv_eigh(dense.laplacian(g))
+    c_true = dense.closeness(Ld)
+    k_true = dense.kemeny_spectral(g)
+    _, diag, _, k, _ = _er256_run(1)
+    c, _ = estimators.closeness(diag)
+    assert abs(k - k_true) / k_true > 1e-2                       # the fresh-walk miss, as measured
+    assert np.mean(np.abs(c - c_true) / c_true) > 1e-2
+    _, diag, _, k, kse = _er256_loop_run(1)
+    c, _ = estimators.closeness(diag)
+    rel = np.abs(c - c_true) / c_true
+    assert abs(k - k_true) / k_true < 1e-2
+    assert rel.mean() < 1e-2 and rel.max() < 1e-2
