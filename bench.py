@@ -371,7 +371,8 @@ def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
 def bench_gather(lap):
     """Random 8-byte gather rates at three working sets: the pointer chase over
     lanes 2^14..2^22, independent loads over lanes {2^14, 2^16, 2^18, 2^20} x
-    loads in flight {1, 2, 4, 8, 16}; the peak of each tier is the maximum."""
+    loads in flight {1, 2, 4, 8, 16}; the peak of each tier is the maximum,
+    at 4 GiB over the four load flavours as well."""
     tiers = {}
     for label, nbytes in (("4MiB", 4 << 20), ("128MiB", 128 << 20), ("4GiB", 4 << 30)):
         chase = {str(1 << lg): lap.bench_gather(nbytes, 1 << lg, 1) for lg in range(14, 23)}
@@ -388,6 +389,11 @@ def bench_gather(lap):
     flavors = {name: {"chase": lap.bench_gather(4 << 30, 1 << 19, 1, 1, fl),
                       "independent": lap.bench_gather(4 << 30, 1 << 18, 0, 8, fl)}
                for fl, name in enumerate(("plain", "nontemporal", "atomic_device", "atomic_system"))}
+    # the 4 GiB peak is the highest rate of any flavour: non-temporal loads
+    # run a few percent above plain ones there
+    t4 = tiers["4GiB"]
+    t4["plain_peak"] = t4["peak"]
+    t4["peak"] = max(t4["peak"], max(max(v.values()) for v in flavors.values()))
     return {"unit": "random 8-byte loads/s (one memory request each at the 4 GiB tier)", "tiers": tiers,
             "flavors_4GiB": flavors}
 
