@@ -229,11 +229,12 @@ def timed_steps(lap, g, omega, root, steps, warmup, B=64, walks=0):
     lap.prof_enable(False)
     st = g.last_stats()
     kern = {}
-    for name in ("wilson_group", "wilson_wave", "wilson_lane", "absorbed", "loop_included", "assemble"):
+    for name in ("wilson_group", "wilson_wave", "wilson_lane", "wilson_lds", "absorbed", "loop_included",
+                 "assemble"):
         ms, n = lap.prof_read(name)
         if n:
             kern[name] = {"ms_avg": ms / n, "launches": n}
-    wk = next(k for k in ("wilson_group", "wilson_wave", "wilson_lane") if k in kern)
+    wk = next(k for k in ("wilson_group", "wilson_wave", "wilson_lane", "wilson_lds") if k in kern)
     return dt, st, kern, wk, out
 
 

@@ -104,7 +104,13 @@ enum {
                                  the device run on a large graph */
     LAP_MODE_LANE = 1,        /* one lane per sample, walks run one after another */
     LAP_MODE_WAVE = 2,        /* one wavefront per sample, 64 concurrent walkers */
-    LAP_MODE_GROUP = 3        /* one workgroup of 2, 4 or 8 wavefronts per sample, 64 walkers each */
+    LAP_MODE_GROUP = 3,       /* one workgroup of 2, 4 or 8 wavefronts per sample, 64 walkers each */
+    LAP_MODE_LDS = 4          /* one lane per sample with the CSR and the samples' state in LDS: graphs
+                                 of at most 1024 nodes whose columns and state fit (lap_sample_forests,
+                                 lap_sample_forests_noalloc and lap_estimate with fresh walks only;
+                                 calls that read the trees back from device memory reject it).  Each
+                                 sample is one sequential chain, so it pays on graphs whose walks are
+                                 long (grids, paths), not where the wave form's walkers share them */
 };
 
 typedef struct {
@@ -119,7 +125,8 @@ typedef struct {
     int64_t n_total;       /* samples of the whole run; block of sample i = floor(i*B/n_total);
                               0 = sample_begin + n_samples */
     int32_t mode;          /* LAP_MODE_* */
-    int32_t pool;          /* concurrent samples (slots); 0 = automatic */
+    int32_t pool;          /* concurrent samples (slots); 0 = automatic (the LDS form: all samples,
+                              at most 2^16 workgroups) */
     double timeout_s;      /* kernel time limit; 0 = 120 s */
     int64_t schedule;      /* wave and workgroup forms: the start scan begins at node (schedule mod n)
                               and wraps; counts do not depend on it (a knob for schedule-randomised tests) */
@@ -536,7 +543,7 @@ const char *lap_last_error(void);
 /* Kernel timing: when enabled, every kernel launch of the library is
  * bracketed by HIP events on the stream it runs on; lap_prof_read returns
  * the accumulated milliseconds and launch count for a kernel name
- * ("wilson_wave", "wilson_lane", "wilson_group", "spantree", "loop_included",
+ * ("wilson_wave", "wilson_lane", "wilson_group", "wilson_lds", "spantree", "loop_included",
  * "pair_paths", "pair_assemble", "lv_rows", "absorbed", "assemble",
  * "batch", "batch_assemble").  Returns
  * LAP_EINVAL for an unknown name. */

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "liblap.so")
 LAP_OK, LAP_EINVAL, LAP_ENOTCONN, LAP_ENOMEM, LAP_EDEVICE, LAP_ERANGE, LAP_ECANCELED = 0, -1, -2, -3, -4, -5, -6
 LAP_KEEP_LCC, LAP_DEGREE_ORDER = 1, 2
 LAP_WANT_Y1, LAP_WANT_Y2_UNIFORM, LAP_WANT_Y2_PI, LAP_WANT_PER_SAMPLE, LAP_OUT_DEVICE = 1, 2, 4, 8, 16
-LAP_MODE_AUTO, LAP_MODE_LANE, LAP_MODE_WAVE, LAP_MODE_GROUP = 0, 1, 2, 3
+LAP_MODE_AUTO, LAP_MODE_LANE, LAP_MODE_WAVE, LAP_MODE_GROUP, LAP_MODE_LDS = 0, 1, 2, 3, 4
 
 # every symbol include/lap.h declares
 EXPORTS = [

@@ -61,6 +61,9 @@ extern "C" int lap_build_csr(int64_t n, int64_t n_edges, const int32_t *src, con
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
         g->clock_khz = khz;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+        g->lds_per_block = lds;
     auto upload = [&](DevBuf &b, const void *src_, size_t bytes) -> int {
         if (b.ensure(bytes) != LAP_OK) return LAP_ENOMEM;
         if (bytes && hipMemcpyAsync(b.ptr, src_, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
@@ -130,15 +133,23 @@ extern "C" int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t
 // --------------------------------------------------------------- sampling
 namespace lap {
 
+int32_t lds_lanes(const lap_graph *g) {
+    const int64_t n = g->csr.n;
+    if (n > kLdsMaxNodes) return 0;
+    for (int32_t lanes = 64; lanes >= 16; lanes /= 2)
+        if (lds_bytes(n, g->csr.rp[n], lanes) <= g->lds_per_block) return lanes;
+    return 0;
+}
+
 int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, const int64_t *keep_idx,
-                 Resolved &r) {
+                 Resolved &r, bool reads_trees) {
     const int64_t n = g->csr.n;
     if (!a) return fail(LAP_EINVAL, "args is NULL");
     if (a->n_samples < 1) return fail(LAP_EINVAL, "n_samples must be >= 1");
     if (a->root < -1 || a->root >= n) return fail(LAP_EINVAL, "root out of range");
     if (a->n_blocks < 1) return fail(LAP_EINVAL, "n_blocks must be >= 1");
     if (a->sample_begin < 0) return fail(LAP_EINVAL, "sample_begin must be >= 0");
-    if (a->mode < LAP_MODE_AUTO || a->mode > LAP_MODE_GROUP) return fail(LAP_EINVAL, "unknown mode");
+    if (a->mode < LAP_MODE_AUTO || a->mode > LAP_MODE_LDS) return fail(LAP_EINVAL, "unknown mode");
     if (a->group != 0 && a->group != 2 && a->group != 4 && a->group != 8)
         return fail(LAP_EINVAL, "group must be 0, 2, 4 or 8");
     if (a->pool < 0) return fail(LAP_EINVAL, "pool must be >= 0");
@@ -163,6 +174,16 @@ int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, c
     // a large graph, several waves share a sample instead (workgroup form)
     const int64_t wave_slots = (int64_t)g->n_cu * 16;
     r.mode = a->mode;
+    r.lds_lanes = reads_trees ? 0 : lds_lanes(g);
+    if (r.mode == LAP_MODE_LDS) {
+        if (reads_trees)
+            return fail(LAP_EINVAL, "this call reads the Wilson trees from device memory; the LDS form keeps "
+                                    "them in LDS only: use the lane, wave or workgroup form");
+        if (r.lds_lanes == 0)
+            return fail(LAP_ERANGE, "the LDS form takes graphs of at most " + std::to_string(kLdsMaxNodes) +
+                                        " nodes whose columns and state for 16 samples fit in " +
+                                        std::to_string(g->lds_per_block) + " bytes of LDS");
+    }
     if (r.mode == LAP_MODE_AUTO)
         r.mode = (r.omega * 4 <= wave_slots && n >= (1 << 16)) ? LAP_MODE_GROUP : LAP_MODE_WAVE;
     r.group = 0;
@@ -172,6 +193,11 @@ int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, c
             r.group = 2;
             while (r.group < 8 && r.omega * r.group * 2 <= wave_slots) r.group *= 2;
         }
+    }
+    if (r.mode == LAP_MODE_LDS) {
+        // concurrent samples: the pool, else all of them (state lives in LDS)
+        r.slots = std::max<int64_t>(1, std::min<int64_t>(r.omega, a->pool > 0 ? a->pool : r.omega));
+        return LAP_OK;
     }
     // concurrent sample slots: bounded by the samples, the pool and a state
     // budget of 48 GiB (8 bytes per node per slot)
@@ -307,8 +333,10 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
     for (int64_t done = 0; r.wilson && done < r.omega; done += round) {
         const int64_t rows = std::min(round, r.omega - done);
         const int64_t slots = loop ? rows : std::min(r.slots, rows);
-        int rc = ensure_state(g, slots, s);
-        if (rc != LAP_OK) return rc;
+        if (r.mode != LAP_MODE_LDS) {
+            int rc = ensure_state(g, slots, s);
+            if (rc != LAP_OK) return rc;
+        }
         WilsonParams wp;
         std::memset(&wp, 0, sizeof wp);
         wp.n = n;
@@ -340,6 +368,9 @@ int run_sampling(lap_graph *g, const Resolved &r, const lap_sample_args *a, int6
         if (r.mode == LAP_MODE_LANE) {
             tm.begin("wilson_lane", s);
             HIP_TRY(launch_wilson_lane(wp, wp.n_slots, s));
+        } else if (r.mode == LAP_MODE_LDS) {
+            tm.begin("wilson_lds", s);
+            HIP_TRY(launch_wilson_lds(wp, r.lds_lanes, wp.n_slots, s));
         } else if (r.mode == LAP_MODE_GROUP) {
             tm.begin("wilson_group", s);
             HIP_TRY(launch_wilson_group(wp, wp.n_slots, r.group, s));
@@ -469,7 +500,7 @@ extern "C" int lap_estimate(lap_graph *g, const lap_sample_args *a, lap_estimate
     if (!g) return fail(LAP_EINVAL, "graph is NULL");
     if (!out) return fail(LAP_EINVAL, "out is NULL");
     Resolved r;
-    int rc = resolve_args(g, a, 0, nullptr, r);
+    int rc = resolve_args(g, a, 0, nullptr, r, a && a->walks == LAP_WALKS_LOOP);
     if (rc != LAP_OK) return rc;
     if (r.begin != 0 || r.total != r.omega)
         return fail(LAP_EINVAL, "lap_estimate runs a whole sample set: sample_begin = 0, n_total = n_samples");
@@ -613,7 +644,7 @@ extern "C" int lap_spantree(lap_graph *g, const lap_sample_args *a, int64_t *X1,
                             int64_t *s2, void *hip_stream) {
     if (!g) return fail(LAP_EINVAL, "graph is NULL");
     Resolved r;
-    int rc = resolve_args(g, a, 0, nullptr, r);
+    int rc = resolve_args(g, a, 0, nullptr, r, true);
     if (rc != LAP_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     Timer tm;
@@ -633,7 +664,7 @@ extern "C" int lap_spantree_estimate(lap_graph *g, const lap_sample_args *a, dou
                                      double *closeness, double *kemeny, double *kemeny_se, void *hip_stream) {
     if (!g) return fail(LAP_EINVAL, "graph is NULL");
     Resolved r;
-    int rc = resolve_args(g, a, 0, nullptr, r);
+    int rc = resolve_args(g, a, 0, nullptr, r, true);
     if (rc != LAP_OK) return rc;
     if (r.begin != 0 || r.total != r.omega)
         return fail(LAP_EINVAL, "a SpanTree estimate runs a whole sample set: sample_begin = 0, n_total = n_samples");
@@ -689,7 +720,7 @@ extern "C" int lap_loop_included(lap_graph *g, const lap_sample_args *a, int32_t
     if (!g) return fail(LAP_EINVAL, "graph is NULL");
     if (tag != 1 && tag != 2) return fail(LAP_EINVAL, "tag must be 1 (uniform start) or 2 (stationary start)");
     Resolved r;
-    int rc = resolve_args(g, a, 0, nullptr, r);
+    int rc = resolve_args(g, a, 0, nullptr, r, true);
     if (rc != LAP_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     Timer tm;
@@ -915,7 +946,7 @@ extern "C" int lap_pair_paths(lap_graph *g, const lap_sample_args *a, const int3
     if (check != 0 && check != 1) return fail(LAP_EINVAL, "check must be 0 or 1");
     if (lanes < 0) return fail(LAP_EINVAL, "lanes must be >= 0");
     Resolved r;
-    int rc = resolve_args(g, a, 0, nullptr, r);
+    int rc = resolve_args(g, a, 0, nullptr, r, true);
     if (rc != LAP_OK) return rc;
     const int64_t n = g->csr.n;
     for (int64_t j = 0; j < n_pairs; ++j)
@@ -965,7 +996,7 @@ extern "C" int lap_lv_rows(lap_graph *g, const lap_sample_args *a, const int32_t
     if (check != 0 && check != 1) return fail(LAP_EINVAL, "check must be 0 or 1");
     if (lanes < 0) return fail(LAP_EINVAL, "lanes must be >= 0");
     Resolved r;
-    int rc = resolve_args(g, a, 0, nullptr, r);
+    int rc = resolve_args(g, a, 0, nullptr, r, true);
     if (rc != LAP_OK) return rc;
     const int64_t n = g->csr.n;
     for (int64_t j = 0; j < n_sources; ++j)

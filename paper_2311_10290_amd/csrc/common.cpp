@@ -27,9 +27,9 @@ struct ProfEntry {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::map<std::string, ProfEntry> g_prof;
-const char *kKernelNames[] = {"wilson_wave", "wilson_lane",    "wilson_group", "spantree", "loop_included",
-                              "pair_paths",  "pair_assemble", "lv_rows",      "absorbed", "assemble",
-                              "batch",       "batch_assemble"};
+const char *kKernelNames[] = {"wilson_wave", "wilson_lane",    "wilson_group", "wilson_lds", "spantree",
+                              "loop_included", "pair_paths", "pair_assemble", "lv_rows", "absorbed",
+                              "assemble",    "batch",         "batch_assemble"};
 }  // namespace
 
 Timer::Timer() {

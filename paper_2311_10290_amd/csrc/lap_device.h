@@ -68,6 +68,25 @@ __device__ __forceinline__ uint32_t st_tag(uint64_t w, uint32_t ep) {
     return st_current(w, ep) ? (uint32_t)((w >> 53) & 0x3FFu) : kTagFree;
 }
 
+// ------------------------------------------------------------ LDS lane form
+// The LDS-resident lane form keeps the CSR and one 32-bit word per node for
+// each of its lanes' samples in LDS:
+//   bits  0..9   next (graphs of at most kLdsMaxNodes nodes)
+//   bit   10     in tree
+//   bits 11..31  k (draws made at the node in this sample, at most kMaxDraws)
+// LDS layout in 32-bit words: row offsets [n + 1], 16-bit columns [nnz]
+// (padded to a whole word), then the state, node-major: word u * lanes + lane.
+constexpr int64_t kLdsMaxNodes = 1024;
+constexpr uint32_t kLdsTree = 1u << 10;
+constexpr int kLdsKShift = 11;
+static_assert(kLdsMaxNodes <= (int64_t)kLdsTree, "next must fit below the tree bit");
+static_assert(((uint64_t)kMaxDraws << kLdsKShift) <= 0xFFFFFFFFull, "k must fit above the tree bit");
+
+__host__ __device__ inline int64_t lds_state_offset(int64_t n, int64_t nnz) { return (n + 1) + (nnz + 1) / 2; }
+__host__ __device__ inline int64_t lds_bytes(int64_t n, int64_t nnz, int64_t lanes) {
+    return 4 * (lds_state_offset(n, nnz) + n * lanes);
+}
+
 // ------------------------------------------------------------ error reporting
 enum : int32_t { kErrNone = 0, kErrDrawOverflow = 1, kErrTimeout = 2, kErrInconsistent = 3 };
 

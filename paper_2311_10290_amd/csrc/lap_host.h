@@ -42,12 +42,20 @@ int fail(int code, const std::string &msg);
 struct Resolved {
     int64_t omega, begin, total;
     int32_t root, B, mode, group;
+    int32_t lds_lanes;   // LDS lane form: samples per workgroup
     int64_t slots;
     bool wilson, y2u, y2p;
 };
 
+// reads_trees: the call reads the Wilson trees back from the state slots
+// (SpanTree, loop-included paths), so the LDS lane form, which keeps its state
+// in LDS only, is refused and never chosen automatically.
 int resolve_args(const lap_graph *g, const lap_sample_args *a, int64_t n_keep, const int64_t *keep_idx,
-                 Resolved &r);
+                 Resolved &r, bool reads_trees = false);
+
+// Samples per workgroup of the LDS lane form on this graph (64, 32 or 16), or
+// 0 when the graph has too many nodes or its columns and state do not fit.
+int32_t lds_lanes(const lap_graph *g);
 
 // Status and error text for a device-side error word (LAP_OK when clear).
 int status_from_err(const DevErr &e);
@@ -94,6 +102,7 @@ struct lap_graph {
     int device = 0;
     int n_cu = 256;
     double clock_khz = 100000.0;
+    int64_t lds_per_block = 65536;   // LDS bytes a workgroup may use
     lap::HostCSR csr;
     int32_t max_deg_node = 0, max_deg = 0;
     lap::DevBuf rp, nbr, col, arcs;   // arcs: per column entry {target, its adjacency record}, large graphs only

@@ -10,6 +10,10 @@
 namespace lap {
 
 hipError_t launch_wilson_lane(const WilsonParams &p, int64_t slots, hipStream_t s);
+// lanes: samples per workgroup (one wavefront), with lds_bytes(n, nnz, lanes)
+// of LDS; slots: samples run at once (at most 2^16 workgroups), each lane
+// taking every slots-th sample; p.state and p.slot_epoch are not used
+hipError_t launch_wilson_lds(const WilsonParams &p, int lanes, int64_t slots, hipStream_t s);
 hipError_t launch_wilson_wave(const WilsonParams &p, int64_t slots, hipStream_t s);
 hipError_t launch_wilson_group(const WilsonParams &p, int64_t slots, int waves, hipStream_t s);
 hipError_t launch_absorbed(const AbsorbedParams &p, hipStream_t s);

@@ -96,14 +96,16 @@ extern "C" int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a
     r.y2p = (a->want & LAP_WANT_Y2_PI) && out->y2len_pi;
 
     // concurrent sample slots: as many as the walk state leaves room for in
-    // the scratch (each slot: n state words and half an epoch word)
+    // the scratch (each slot: n state words and half an epoch word); the LDS
+    // lane form keeps its state in LDS and needs none
+    const bool in_lds = r.mode == LAP_MODE_LDS;
     const int64_t room = kScratchWords - kOffEpochs - 1 - 32;   // the epoch word rounding and the alignment
     const int64_t fit = 2 * room / (2 * std::max<int64_t>(n, 1) + 1);
-    if (r.wilson && fit < 1)
+    if (r.wilson && !in_lds && fit < 1)
         return fail(LAP_ERANGE, "a graph of " + std::to_string(n) + " nodes needs more walk state than the " +
                                     std::to_string(kScratchWords * 8 >> 20) + " MiB fixed scratch holds (at most " +
                                     std::to_string(room - 1) + " nodes)");
-    const int64_t slots = std::max<int64_t>(1, std::min(r.slots, fit));
+    const int64_t slots = in_lds ? r.slots : std::max<int64_t>(1, std::min(r.slots, fit));
 
     uint64_t *sc = nullptr;
     if ((rc = scratch_on_device(dev, &sc)) != LAP_OK) return rc;
@@ -114,7 +116,8 @@ extern "C" int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a
     uint32_t *epochs = reinterpret_cast<uint32_t *>(sc + kOffEpochs);
     const int64_t off_state = (kOffEpochs + epoch_words + 31) / 32 * 32;
     uint64_t *state = sc + off_state;
-    if (r.wilson && off_state + slots * n > kScratchWords) return fail(LAP_EINVAL, "scratch layout overflow");
+    if (r.wilson && !in_lds && off_state + slots * n > kScratchWords)
+        return fail(LAP_EINVAL, "scratch layout overflow");
 
     hipStream_t s = (hipStream_t)hip_stream;
     // the scratch keeps the last call's contents: clear what must start at zero
@@ -154,8 +157,10 @@ extern "C" int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a
         HIP_TRY(launch_absorbed(ap, s));
     }
     if (r.wilson) {
-        HIP_TRY(launch_fill_u64(sc + kOffEpochs, 0ull, epoch_words, s));
-        HIP_TRY(launch_fill_u64(state, 0ull, slots * n, s));
+        if (!in_lds) {
+            HIP_TRY(launch_fill_u64(sc + kOffEpochs, 0ull, epoch_words, s));
+            HIP_TRY(launch_fill_u64(state, 0ull, slots * n, s));
+        }
         WilsonParams wp;
         std::memset(&wp, 0, sizeof wp);
         wp.n = n;
@@ -186,6 +191,8 @@ extern "C" int lap_sample_forests_noalloc(lap_graph *g, const lap_sample_args *a
         wp.scan_offset = n > 0 ? ((a->schedule % n) + n) % n : 0;
         if (r.mode == LAP_MODE_LANE) {
             HIP_TRY(launch_wilson_lane(wp, slots, s));
+        } else if (in_lds) {
+            HIP_TRY(launch_wilson_lds(wp, r.lds_lanes, slots, s));
         } else if (r.mode == LAP_MODE_GROUP) {
             HIP_TRY(launch_wilson_group(wp, slots, r.group, s));
         } else {

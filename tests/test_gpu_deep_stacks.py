@@ -7,8 +7,10 @@ later draw stored and next pointers followed).  Expected draws at u are
 N_uu = d_u r(u, v) (Sec. 3.3), so the path P_200 rooted at one end (N_uu = 2u
 inside the path) and the 2 x 100 ladder rooted at a corner reach that branch
 in most samples.  Every count, both walk kinds and every kept tree must equal
-the oracle's bit for bit in the lane, wave and workgroup forms, and the
-oracle's own draws show that the branch was taken."""
+the oracle's bit for bit in the lane, wave, workgroup and LDS forms, and the
+oracle's own draws show that the branch was taken (the LDS form keeps 21-bit
+draw counts in its state words and has no such branch; it runs the same
+cases)."""
 import numpy as np
 import pytest
 
@@ -19,7 +21,7 @@ from tests.test_gpu_parity import _oracle_counts, _same
 
 pytestmark = pytest.mark.gpu
 
-LANE, WAVE, GROUP = 1, 2, 3
+LANE, WAVE, GROUP, LDS = 1, 2, 3, 4
 OMEGA = 64
 
 
@@ -30,7 +32,7 @@ def _graph(name, *args):
 
 
 CASES = [("path200", _graph("path", 200)), ("ladder2x100", _graph("grid", 2, 100))]
-FORMS = [(LANE, 0), (WAVE, 0), (GROUP, 2), (GROUP, 4), (GROUP, 8)]
+FORMS = [(LANE, 0), (WAVE, 0), (GROUP, 2), (GROUP, 4), (GROUP, 8), (LDS, 0)]
 
 
 @pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])

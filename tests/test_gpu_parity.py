@@ -9,7 +9,7 @@ from tests.gpu_common import ba_edges, both, er256_edges, log, small_cases
 
 pytestmark = pytest.mark.gpu
 
-MODES = [1, 2]          # LAP_MODE_LANE, LAP_MODE_WAVE
+MODES = [1, 2, 4]       # LAP_MODE_LANE, LAP_MODE_WAVE, LAP_MODE_LDS
 
 
 def _oracle_counts(og, root, omega, seed, B=1, keep=(), begin=0, total=None, uniform=True, pi=True):
@@ -278,11 +278,13 @@ def test_profiling_counters():
     _, hg = both(n, s, d)
     prof_reset()
     prof_enable(True)
-    hg.estimate(256, 1)
+    hg.estimate(256, 1)                 # automatic mode: the wave form
+    hg.estimate(256, 1, mode=4)
     prof_enable(False)
-    ms, cnt = prof_read("wilson_wave")
-    assert cnt == 1 and ms > 0
+    for name in ("wilson_wave", "wilson_lds"):
+        ms, cnt = prof_read(name)
+        assert cnt == 1 and ms > 0, name
     ms, cnt = prof_read("absorbed")
-    assert cnt == 1 and ms > 0          # both walk kinds in one launch
+    assert cnt == 2 and ms > 0          # both walk kinds in one launch per call
     st = hg.last_stats()
     assert st["trees"] == 256 and st["wilson_steps"] > 0 and st["absorbed_steps"] > 0

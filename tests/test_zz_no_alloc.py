@@ -1,7 +1,7 @@
 """lap_sample_forests_noalloc (the entry point whose scratch is a fixed device
 array) against lap_sample_forests: the same counts bit for bit, on two calls
 in a row where the second has a smaller graph and sample count (the scratch
-keeps the first call's contents), in the wave, lane and workgroup forms;
+keeps the first call's contents), in the wave, lane, workgroup and LDS forms;
 sizes beyond the fixed scratch are refused before anything runs."""
 import numpy as np
 import pytest
@@ -34,8 +34,9 @@ def test_noalloc_equals_plain_call_twice_second_smaller():
     small = Graph(256, s, d)
     log("noalloc: ER 256, 300 samples after the larger call")
     _compare(small, 300, 1, -1, B=4, keep=[0, 299])
-    log("noalloc: ER 256, lane and workgroup forms")
+    log("noalloc: ER 256, lane, LDS and workgroup forms")
     _compare(small, 200, 2, 7, B=3, keep=[5], mode=1)
+    _compare(small, 300, 1, -1, B=4, keep=[0, 299], mode=4)
     _compare(small, 90, 4, -1, B=2, keep=[89], mode=3, group=4)
     log("noalloc: BA 30000 again, fewer samples")
     _compare(big, 129, 8, -1, B=1, keep=[128])
