@@ -32,6 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# vector ALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes wide), at 2.4 GHz
+VALU_PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
 WILSON_BYTES_PER_STEP = 33.0     # offsets 16 + column 4 + draw count 8 + next 4 + tree flag 1
 RETRACE_BYTES_PER_NODE = 5.0
 SEED = 1
@@ -102,7 +105,9 @@ def write_traffic(pmc_dir, which):
     and WRITE_SIZE), plus <which>_fetch/bench.json (the run's JSON line, for
     the draws per launch), and optionally <which>_tcc/ with TCC_HIT_sum
     TCC_MISS_sum TCC_REQ_sum TCP_TCC_READ_REQ_sum TCP_TCC_WRITE_REQ_sum (the
-    L1-to-L2 requests).  Each byte count is scaled by the copy's bytes over
+    L1-to-L2 requests) and <which>_valu/ with SQ_INSTS_VALU and
+    SQ_INSTS_VALU_INT64 (vector instructions issued, 64-bit integer ones among
+    them).  Each byte count is scaled by the copy's bytes over
     what the same counters read for the copy; several launches of the kernel
     in one run are averaged."""
     def fetch_bytes(c):
@@ -139,6 +144,12 @@ def write_traffic(pmc_dir, which):
         t = mean(_csv_counters(tcc_dir, spec["kernel"]))
         res["l2"] = {"counters": t, "l1_to_l2_read_requests_per_draw": t["TCP_TCC_READ_REQ_sum"] / draws,
                      "l2_hit_rate": t["TCC_HIT_sum"] / max(t["TCC_REQ_sum"], 1.0)}
+    valu_dir = os.path.join(pmc_dir, f"{which}_valu")
+    if os.path.isdir(valu_dir):
+        v = mean(_csv_counters(valu_dir, spec["kernel"]))
+        res["valu"] = {"counters": v, "instructions_per_launch": v["SQ_INSTS_VALU"],
+                       "instructions_per_draw": v["SQ_INSTS_VALU"] / draws,
+                       "int64_share": v["SQ_INSTS_VALU_INT64"] / max(v["SQ_INSTS_VALU"], 1.0)}
     res["bytes_per_launch"] = res["fetch"]["bytes"] + res["write"]["bytes"]
     res["bytes_per_draw"] = res["bytes_per_launch"] / draws
     res["read_requests_per_draw"] = res["read_requests_per_launch"] / draws
@@ -246,6 +257,17 @@ def roofline(st, n, kern_ms, traffic, kernel):
             "kernel": kernel, "bytes_per_launch": alg, "kernel_ms": kern_ms}
 
 
+def valu_rate(traffic, kern_ms):
+    """Vector instructions issued per second (counted) against the issue peak."""
+    if not traffic or "valu" not in traffic:
+        return None
+    rate = traffic["valu"]["instructions_per_launch"] / (kern_ms * 1e-3)
+    return {"bound": "alu", "achieved": rate / 1e9, "peak": VALU_PEAK_WAVE_INSTR / 1e9,
+            "unit": "G wave64 VALU instructions/s", "frac": rate / VALU_PEAK_WAVE_INSTR,
+            "instructions_per_draw": traffic["valu"]["instructions_per_draw"],
+            "int64_share": traffic["valu"]["int64_share"]}
+
+
 def request_rate(traffic, kern_ms, gather):
     """Read requests per second that reach memory (L2 misses, counted) against
     the measured random-request peak at the 4 GiB tier."""
@@ -291,6 +313,9 @@ def bench_small(lap, gg, steps, warmup, with_cpu, gather):
     # reference is the L2-tier random-request rate of the sweep, against the
     # kernel's counted L1-to-L2 read requests
     traffic = measured_traffic("small")
+    # everything sits in the caches and the generator runs once per draw: the
+    # vector ALU issue rate is the roofline that applies
+    res["roofline"] = valu_rate(traffic, kms)
     if gather and traffic and "l2" in traffic:
         per = traffic["l2"]["l1_to_l2_read_requests_per_draw"]
         rate = per * st["wilson_steps"] / (kms * 1e-3)
@@ -360,7 +385,7 @@ def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
            "absorbed_steps_per_step": st["absorbed_steps"],
            "kernel_ms": {k: v["ms_avg"] for k, v in kern.items()},
            "roofline": roofline(st, g.n, kms, traffic, TRAFFIC["mid"]["kernel"]),
-           "requests": request_rate(traffic, kms, gather),
+           "requests": request_rate(traffic, kms, gather), "valu": valu_rate(traffic, kms),
            "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
     if with_cpu:
         from oracle import csr as ocsr
@@ -858,7 +883,7 @@ def main():
             "wilson_steps_per_tree_over_n": st["wilson_steps"] / omega / g.n,
             "kernel_ms": {k: v["ms_avg"] for k, v in kern.items()},
             "roofline": roofline(st, g.n, kms, traffic, TRAFFIC["large"]["kernel"]),
-            "requests": request_rate(traffic, kms, gather),
+            "requests": request_rate(traffic, kms, gather), "valu": valu_rate(traffic, kms),
             "estimates": {"kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item()),
                           "trace_Ldagger": float(out["trace"].item())},
         })
