@@ -279,6 +279,17 @@ def request_rate(traffic, kern_ms, gather):
     if gather:
         peak = gather["tiers"]["4GiB"]["peak"]
         out["frac_of_random_request_peak_4GiB"] = rps / peak
+    # reads and writes together against the mixed sweep at the nearest write share
+    wr = traffic["write"]["counters"].get("TCC_EA0_WRREQ_sum")
+    if wr is not None:
+        ratio = wr / max(traffic["read_requests_per_launch"], 1.0)
+        out["writes_per_read"] = ratio
+        out["read_write_requests_per_s"] = (traffic["read_requests_per_launch"] + wr) / (kern_ms * 1e-3)
+        if gather:
+            # against the highest random-request rate measured at 4 GiB (the
+            # read-only one: random stores only lower the sweep's rates)
+            out["read_write_frac_of_random_request_peak_4GiB"] = (out["read_write_requests_per_s"] /
+                                                                   gather["tiers"]["4GiB"]["peak"])
     return out
 
 
@@ -420,8 +431,21 @@ def bench_gather(lap):
     t4 = tiers["4GiB"]
     t4["plain_peak"] = t4["peak"]
     t4["peak"] = max(t4["peak"], max(max(v.values()) for v in flavors.values()))
+    # loads mixed with random stores (one per round of d loads) at 4 GiB, by
+    # write share: 8-byte stores reach memory as 32-byte partial writes, line
+    # stores as 64-byte writes.  Uniformly random stores cost more than the
+    # walkers' write-backs, so these rates are context, not a ceiling.
+    mixed = {}
+    for mode, label in ((2, "stores_8B"), (3, "stores_64B_lines")):
+        sweep = {f"{1 << lg}x{d}": lap.bench_gather(4 << 30, 1 << lg, mode, d) for lg in (16, 18, 20)
+                 for d in (1, 2, 4, 8)}
+        by_ratio = {str(1.0 / d): max(v for k, v in sweep.items() if k.endswith(f"x{d}")) for d in (1, 2, 4, 8)}
+        mixed[label] = {"sweep": sweep, "best_by_writes_per_read": by_ratio}
+        log(f"gather 4GiB with {label}: " + ", ".join(f"{float(r):.3f} writes/read {v / 1e9:.1f} G/s"
+                                                      for r, v in by_ratio.items()))
+    mixed["unit"] = "random loads + stores per second (one memory request each)"
     return {"unit": "random 8-byte loads/s (one memory request each at the 4 GiB tier)", "tiers": tiers,
-            "flavors_4GiB": flavors}
+            "flavors_4GiB": flavors, "with_stores_4GiB": mixed}
 
 
 def bench_batch(lap, gg, n_jobs, with_cpu):

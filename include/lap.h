@@ -560,16 +560,18 @@ int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_
                    int64_t *idle_lane_rounds, int64_t *parked_lane_rounds);
 
 /* Random-gather rate of the current device, the roofline reference for the
- * walkers: loads per second (written to *rate) of random 8-byte loads over a
- * working set of `bytes` (>= 1 MiB, rounded down to a power of two) by
- * `lanes` (256 .. 2^24) concurrent lanes.  mode 0: each lane issues
+ * walkers: memory operations per second (written to *rate) of random 8-byte
+ * accesses over a working set of `bytes` (>= 1 MiB, rounded down to a power
+ * of two) by `lanes` (256 .. 2^24) concurrent lanes.  mode 0: each lane issues
  * `in_flight` (1, 2, 4, 8 or 16) independent loads per round; mode 1: each lane
  * follows a dependent pointer chain through a random cyclic order of 64-byte
- * lines (in_flight must be 1, 2, 4, 8 or 16 and is ignored).  flavor: 0 plain
- * loads, 1 non-temporal loads, 2 relaxed atomic loads at device scope, 3 at
- * system scope.  A sweep over lanes and in_flight gives each working-set
- * tier's peak.  Allocates and frees its own buffer; LAP_EINVAL on bad
- * arguments. */
+ * lines (in_flight must be 1, 2, 4, 8 or 16 and is ignored); mode 2: as mode 0
+ * plus one random 8-byte store per round; mode 3: as mode 0 plus one store of a
+ * whole random 64-byte line per round (modes 2 and 3 count loads and stores, a
+ * line store once, and take plain loads only).  flavor: 0 plain loads, 1 non-temporal loads, 2 relaxed atomic
+ * loads at device scope, 3 at system scope.  A sweep over lanes and in_flight
+ * gives each working-set tier's peak.  Allocates and frees its own buffer;
+ * LAP_EINVAL on bad arguments. */
 int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int32_t in_flight, int32_t flavor,
                      double *rate, void *hip_stream);
 

@@ -455,9 +455,11 @@ class Server:
 
 
 def bench_gather(bytes_, lanes, mode, in_flight=1, flavor=0, stream=None):
-    """Random 8-byte loads per second over a working set (mode 0 independent
-    with in_flight loads per lane and round, 1 chase); flavor 0 plain loads,
-    1 non-temporal, 2 / 3 relaxed atomic loads at device / system scope."""
+    """Random 8-byte accesses per second over a working set (mode 0 independent
+    with in_flight loads per lane and round, 1 chase, 2 independent loads plus
+    one 8-byte store per round, 3 plus one 64-byte line store per round, loads
+    and stores counted); flavor 0 plain loads, 1 non-temporal,
+    2 / 3 relaxed atomic loads at device / system scope."""
     r = ctypes.c_double()
     _check(load_library().lap_bench_gather(int(bytes_), int(lanes), int(mode), int(in_flight), int(flavor),
                                            ctypes.byref(r), _stream(stream)))

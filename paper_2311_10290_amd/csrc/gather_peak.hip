@@ -7,8 +7,16 @@
 //                memory system sees up to lanes x in_flight requests at once;
 //   chase:       every lane follows its own pointer chain through a random
 //                cyclic order of 64-byte lines (one dependent load per hop),
-//                the access pattern of a walker.
-// Both report loads per second over a working set of the given size, which
+//                the access pattern of a walker;
+//   mixed:       as independent, plus one random 8-byte store per round, so
+//                one store for every `in_flight` loads (the walkers also
+//                write their state words at random places); a store reaches
+//                memory as a partial (32-byte) write;
+//   mixed lines: as mixed, but the store fills a whole random 64-byte line
+//                (a full-line write, as the evictions of lines the walkers
+//                have written throughout).
+// All report memory operations (loads, and stores in mixed mode) per second
+// over a working set of the given size, which
 // selects the cache tier (L2 4 MB per XCD, 256 MB Infinity Cache, HBM).  A
 // sweep over lanes (and loads in flight) gives the peak of each tier.
 //
@@ -77,6 +85,42 @@ __global__ __launch_bounds__(256) void gather_kernel(const uint64_t *buf, uint64
     if (acc == 0x1234567) sink[0] = acc;
 }
 
+// each round: D random loads, then one random store of their combination to a
+// third random word (its address from another hash of lane and round)
+// (LINE: the store covers the whole 64-byte line of that word)
+template <int D, bool LINE>
+__global__ __launch_bounds__(256) void mixed_kernel(uint64_t *buf, uint64_t n_words, int64_t rounds) {
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t r = 0; r < rounds; ++r) {
+        uint64_t v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            v[j] = buf[mix64(gid * 0x9E3779B97F4A7C15ull + (uint64_t)r * D + j) & (n_words - 1)];
+        uint64_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc ^= v[j];
+        const uint64_t at = mix64(~(gid * 0xD1B54A32D192ED03ull) + (uint64_t)r) & (n_words - 1);
+        if constexpr (LINE) {
+            uint64_t *line = buf + (at & ~7ull);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) line[j] = acc + (uint64_t)j;
+        } else {
+            buf[at] = acc | 1ull;
+        }
+    }
+}
+
+template <bool LINE>
+void launch_mixed(int depth, unsigned grid, hipStream_t s, uint64_t *buf, uint64_t words, int64_t rounds) {
+    switch (depth) {
+        case 1: hipLaunchKernelGGL((mixed_kernel<1, LINE>), dim3(grid), dim3(256), 0, s, buf, words, rounds); break;
+        case 2: hipLaunchKernelGGL((mixed_kernel<2, LINE>), dim3(grid), dim3(256), 0, s, buf, words, rounds); break;
+        case 4: hipLaunchKernelGGL((mixed_kernel<4, LINE>), dim3(grid), dim3(256), 0, s, buf, words, rounds); break;
+        case 8: hipLaunchKernelGGL((mixed_kernel<8, LINE>), dim3(grid), dim3(256), 0, s, buf, words, rounds); break;
+        default: hipLaunchKernelGGL((mixed_kernel<16, LINE>), dim3(grid), dim3(256), 0, s, buf, words, rounds); break;
+    }
+}
+
 template <int F>
 void launch_gather_depth(int depth, unsigned grid, hipStream_t s, const uint64_t *buf, uint64_t words,
                          int64_t rounds, uint64_t *sink) {
@@ -115,7 +159,8 @@ using namespace lap;
 
 extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int32_t in_flight, int32_t flavor,
                                 double *rate, void *hip_stream) {
-    if (bytes < (1 << 20) || lanes < 256 || lanes > ((int64_t)1 << 24) || !rate || (mode != 0 && mode != 1) ||
+    if (bytes < (1 << 20) || lanes < 256 || lanes > ((int64_t)1 << 24) || !rate || mode < 0 || mode > 3 ||
+        (mode >= 2 && flavor != 0) ||
         (in_flight != 1 && in_flight != 2 && in_flight != 4 && in_flight != 8 && in_flight != 16) || flavor < 0 ||
         flavor > 3)
         return LAP_EINVAL;
@@ -134,7 +179,7 @@ extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int3
                        0x2545F4914F6CDD1Dull | 1ull);
     const unsigned grid = (unsigned)((lanes + 255) / 256);
     // work per lane: rounds of in_flight loads, or hops, about 512 loads either way
-    const int64_t work = mode == 0 ? 512 / in_flight : 512;
+    const int64_t work = mode == 1 ? 512 : 512 / in_flight;
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
@@ -142,15 +187,21 @@ extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int3
         (void)hipEventRecord(a, s);
         if (mode == 0)
             launch_gather(flavor, in_flight, grid, s, buf, words, work, sink);
-        else
+        else if (mode == 1)
             launch_chase(flavor, grid, s, buf, n_lines, work, sink);
+        else if (mode == 2)
+            launch_mixed<false>(in_flight, grid, s, buf, words, work);
+        else
+            launch_mixed<true>(in_flight, grid, s, buf, words, work);
         (void)hipEventRecord(b, s);
     }
     if (hipGetLastError() != hipSuccess || hipEventSynchronize(b) != hipSuccess) rc = LAP_EDEVICE;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
-    const double loads = (double)grid * 256.0 * (double)work * (mode == 0 ? (double)in_flight : 1.0);
-    *rate = ms > 0 ? loads / (ms * 1e-3) : 0.0;
+    // loads and stores per round (a line store counts once: one write request)
+    const double per_round = mode == 0 ? (double)in_flight : mode == 1 ? 1.0 : (double)in_flight + 1.0;
+    const double ops = (double)grid * 256.0 * (double)work * per_round;
+    *rate = ms > 0 ? ops / (ms * 1e-3) : 0.0;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     (void)hipFree(buf);
