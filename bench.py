@@ -405,6 +405,31 @@ def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
     return res, g, root
 
 
+def hot_vertex_share(g, omega, samples=64):
+    """What staging the hubs' data in LDS or a cache could serve, from the
+    draw counts of `samples` trees: with nodes numbered by decreasing degree
+    the hubs' arc records open the arc array and their state words open each
+    slot.  A draw at u lands uniformly in u's row, so the share of draws whose
+    arc record lies in the first B bytes is sum_u Y1[u] * frac_u(B) / sum Y1;
+    arrivals at u are expected sum over neighbours w of Y1[w] / d_w, and the
+    share of arrivals at the first K nodes is their sum over the total."""
+    got = g.sample_forests(min(samples, omega), SEED, -1, B=1, per_sample=False)
+    y1 = got["Y1"][0].astype(np.float64)
+    rp, col, _ = g.csr()
+    deg = np.diff(rp).astype(np.float64)
+    total = y1.sum()
+    arcs = {}
+    for label, nbytes in (("64KiB", 64 << 10), ("4MiB", 4 << 20), ("256MiB", 256 << 20)):
+        first = nbytes // 16          # 16-byte arc records
+        frac = np.clip((first - rp[:-1]) / np.maximum(deg, 1.0), 0.0, 1.0)
+        arcs[label] = float((y1 * frac).sum() / total)
+    arrivals = np.bincount(col, weights=np.repeat(y1 / np.maximum(deg, 1.0), np.diff(rp)), minlength=g.n)
+    state = {str(k): float(arrivals[:k].sum() / arrivals.sum()) for k in (768, 8192, 1 << 16)}
+    del col
+    return {"samples": int(min(samples, omega)), "draw_share_of_first_arc_bytes": arcs,
+            "arrival_share_of_first_nodes": state}
+
+
 def bench_gather(lap):
     """Random 8-byte gather rates at three working sets: the pointer chase over
     lanes 2^14..2^22, independent loads over lanes {2^14, 2^16, 2^18, 2^20} x
@@ -922,6 +947,7 @@ def main():
             "path_steps_per_step": stl["absorbed_steps"],
             "kemeny": float(outl["kemeny"].item()), "kemeny_se": float(outl["kemeny_se"].item()),
             "trace_Ldagger": float(outl["trace"].item())}
+        res["hot_vertex_share"] = hot_vertex_share(g, omega)
         g.close()
         if with_cpu:
             log("large: cpu baseline (oracle)")
