@@ -32,6 +32,42 @@ def _graph(rng, i):
     return 1 << scale, s, d, True
 
 
+@pytest.mark.parametrize("case", range(12))
+def test_random_graph_counts_bit_exact_lds_form(case):
+    """The LDS lane form on random graphs it takes (at most 1024 nodes, columns
+    and state in LDS), with random roots, seeds, stream and query ids and pools."""
+    rng = np.random.default_rng(5000 + case)
+    kind = case % 4
+    if kind == 0:
+        n = int(rng.integers(20, 1000))
+        s, d, _ = gg.erdos_renyi_connected(n, float(rng.uniform(8.0, 14.0)) / n, int(rng.integers(1 << 30)))
+    elif kind == 1:
+        n = int(rng.integers(20, 1000))
+        s, d = gg.barabasi_albert(n, int(rng.integers(1, 6)), int(rng.integers(1 << 30)))
+    elif kind == 2:
+        r, c = int(rng.integers(2, 32)), int(rng.integers(2, 32))
+        s, d = gg.grid(r, c)
+        n = r * c
+    else:
+        n = 1 << int(rng.integers(6, 11))
+        s, d = gg.rmat(int(np.log2(n)), 8, seed=int(rng.integers(1 << 30)))
+    og, hg = both(n, s, d, keep_lcc=kind == 3)
+    assert og.n <= 1024 and 4 * ((og.n + 1) + (og.nnz + 1) // 2 + og.n * 16) <= 64 * 1024
+    root = int(rng.integers(0, og.n)) if case % 2 else csr.landmark(og)
+    omega = int(rng.integers(1, 400))
+    seed = int(rng.integers(1 << 62))
+    stream = int(rng.integers(0, 4))
+    qid = int(rng.integers(0, 1 << 40))
+    B = int(rng.integers(1, min(omega, 8) + 1))
+    pool = int(rng.integers(0, 200))
+    keep = sorted({0, omega - 1})
+    log(f"random lds case {case}: n={og.n} nnz={og.nnz} root={root} omega={omega} pool={pool}")
+    got = hg.sample_forests(omega, seed, root, B=B, keep=keep, mode=4, pool=pool, stream_id=stream, qid=qid)
+    w = native.wilson(og, root, omega, seed, stream=stream, qid=qid, B=B, keep=keep)
+    assert np.array_equal(got["Y1"], w["Y1"]) and np.array_equal(got["y1"], w["y1"])
+    assert np.array_equal(got["next"], w["next"]) and np.array_equal(got["draws"], w["draws"])
+
+
 @pytest.mark.parametrize("case", range(24))
 def test_random_graph_counts_bit_exact(case):
     rng = np.random.default_rng(1000 + case)
