@@ -302,6 +302,26 @@ def rmat_graph(lap, gg, scale):
     return g, src, dst
 
 
+def lds_form_rate(lap, g, omega, root, draws, reps=3):
+    """The LDS lane form (graph and state in LDS) on the same samples, against
+    the LDS random-read rate of the device (lap_bench_gather mode 4: a sweep of
+    lanes and reads in flight per round).  A draw of that form makes about six
+    LDS accesses: two row offsets, one column, the state word read and written
+    at the node, the target's state word."""
+    lds_peak = max(lap.bench_gather(1 << 20, 1 << lg, 4, d) for lg in (14, 16, 18, 20) for d in (1, 4, 16))
+    g.sample_forests(omega, SEED, root, B=64, mode=4)
+    lap.prof_reset()
+    lap.prof_enable(True)
+    for _ in range(reps):
+        g.sample_forests(omega, SEED, root, B=64, mode=4)
+    lap.prof_enable(False)
+    ms, n = lap.prof_read("wilson_lds")
+    ms /= max(n, 1)
+    rate = 6.0 * draws / (ms * 1e-3)
+    return {"wilson_lds_kernel_ms": ms, "draws_per_s": draws / (ms * 1e-3), "lds_accesses_per_draw": 6,
+            "lds_accesses_per_s": rate, "lds_random_read_peak": lds_peak, "frac_of_lds_peak": rate / lds_peak}
+
+
 def bench_small(lap, gg, steps, warmup, with_cpu, gather):
     """Small workload: ER(256, 0.05), graph seed 0, resampled until connected,
     root = max degree, omega = 2^14; accuracy against the dense FP64
@@ -327,6 +347,7 @@ def bench_small(lap, gg, steps, warmup, with_cpu, gather):
     # everything sits in the caches and the generator runs once per draw: the
     # vector ALU issue rate is the roofline that applies
     res["roofline"] = valu_rate(traffic, kms)
+    res["lds_form"] = lds_form_rate(lap, g, omega, root, st["wilson_steps"])
     if gather and traffic and "l2" in traffic:
         per = traffic["l2"]["l1_to_l2_read_requests_per_draw"]
         rate = per * st["wilson_steps"] / (kms * 1e-3)

@@ -568,7 +568,9 @@ int lap_last_stats(const lap_graph *g, int64_t *wilson_steps, int64_t *absorbed_
  * lines (in_flight must be 1, 2, 4, 8 or 16 and is ignored); mode 2: as mode 0
  * plus one random 8-byte store per round; mode 3: as mode 0 plus one store of a
  * whole random 64-byte line per round (modes 2 and 3 count loads and stores, a
- * line store once, and take plain loads only).  flavor: 0 plain loads, 1 non-temporal loads, 2 relaxed atomic
+ * line store once, and take plain loads only); mode 4: `in_flight` random
+ * 4-byte reads per round from a 64 KiB table in LDS, rounds dependent (bytes is
+ * then only checked; plain reads only).  flavor: 0 plain loads, 1 non-temporal loads, 2 relaxed atomic
  * loads at device scope, 3 at system scope.  A sweep over lanes and in_flight
  * gives each working-set tier's peak.  Allocates and frees its own buffer;
  * LAP_EINVAL on bad arguments. */

@@ -458,7 +458,8 @@ def bench_gather(bytes_, lanes, mode, in_flight=1, flavor=0, stream=None):
     """Random 8-byte accesses per second over a working set (mode 0 independent
     with in_flight loads per lane and round, 1 chase, 2 independent loads plus
     one 8-byte store per round, 3 plus one 64-byte line store per round, loads
-    and stores counted); flavor 0 plain loads, 1 non-temporal,
+    and stores counted, 4 random 4-byte reads from a 64 KiB LDS table); flavor
+    0 plain loads, 1 non-temporal,
     2 / 3 relaxed atomic loads at device / system scope."""
     r = ctypes.c_double()
     _check(load_library().lap_bench_gather(int(bytes_), int(lanes), int(mode), int(in_flight), int(flavor),

@@ -14,7 +14,11 @@
 //                memory as a partial (32-byte) write;
 //   mixed lines: as mixed, but the store fills a whole random 64-byte line
 //                (a full-line write, as the evictions of lines the walkers
-//                have written throughout).
+//                have written throughout);
+//   lds:         every lane issues `in_flight` independent random 4-byte
+//                reads per round from a 64 KiB table in its workgroup's LDS,
+//                each round's addresses depending on the previous round's
+//                values (the working set is fixed: the LDS random-access rate).
 // All report memory operations (loads, and stores in mixed mode) per second
 // over a working set of the given size, which
 // selects the cache tier (L2 4 MB per XCD, 256 MB Infinity Cache, HBM).  A
@@ -121,6 +125,35 @@ void launch_mixed(int depth, unsigned grid, hipStream_t s, uint64_t *buf, uint64
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void lds_kernel(int64_t rounds, uint64_t *sink) {
+    constexpr int kWords = 16384;   // 64 KiB
+    __shared__ uint32_t tab[kWords];
+    for (int i = (int)threadIdx.x; i < kWords; i += (int)blockDim.x) tab[i] = (uint32_t)mix64((uint64_t)i);
+    __syncthreads();
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (int64_t r = 0; r < rounds; ++r) {
+        uint32_t v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            v[j] = tab[(uint32_t)mix64(gid * 0x9E3779B97F4A7C15ull + (uint64_t)r * D + j + acc) & (kWords - 1)];
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc ^= v[j];
+    }
+    if (acc == 0x1234567u) sink[0] = acc;
+}
+
+void launch_lds(int depth, unsigned grid, hipStream_t s, int64_t rounds, uint64_t *sink) {
+    switch (depth) {
+        case 1: hipLaunchKernelGGL(lds_kernel<1>, dim3(grid), dim3(256), 0, s, rounds, sink); break;
+        case 2: hipLaunchKernelGGL(lds_kernel<2>, dim3(grid), dim3(256), 0, s, rounds, sink); break;
+        case 4: hipLaunchKernelGGL(lds_kernel<4>, dim3(grid), dim3(256), 0, s, rounds, sink); break;
+        case 8: hipLaunchKernelGGL(lds_kernel<8>, dim3(grid), dim3(256), 0, s, rounds, sink); break;
+        default: hipLaunchKernelGGL(lds_kernel<16>, dim3(grid), dim3(256), 0, s, rounds, sink); break;
+    }
+}
+
 template <int F>
 void launch_gather_depth(int depth, unsigned grid, hipStream_t s, const uint64_t *buf, uint64_t words,
                          int64_t rounds, uint64_t *sink) {
@@ -159,7 +192,7 @@ using namespace lap;
 
 extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int32_t in_flight, int32_t flavor,
                                 double *rate, void *hip_stream) {
-    if (bytes < (1 << 20) || lanes < 256 || lanes > ((int64_t)1 << 24) || !rate || mode < 0 || mode > 3 ||
+    if (bytes < (1 << 20) || lanes < 256 || lanes > ((int64_t)1 << 24) || !rate || mode < 0 || mode > 4 ||
         (mode >= 2 && flavor != 0) ||
         (in_flight != 1 && in_flight != 2 && in_flight != 4 && in_flight != 8 && in_flight != 16) || flavor < 0 ||
         flavor > 3)
@@ -191,15 +224,18 @@ extern "C" int lap_bench_gather(int64_t bytes, int64_t lanes, int32_t mode, int3
             launch_chase(flavor, grid, s, buf, n_lines, work, sink);
         else if (mode == 2)
             launch_mixed<false>(in_flight, grid, s, buf, words, work);
-        else
+        else if (mode == 3)
             launch_mixed<true>(in_flight, grid, s, buf, words, work);
+        else
+            launch_lds(in_flight, grid, s, work * 4, sink);
         (void)hipEventRecord(b, s);
     }
     if (hipGetLastError() != hipSuccess || hipEventSynchronize(b) != hipSuccess) rc = LAP_EDEVICE;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
     // loads and stores per round (a line store counts once: one write request)
-    const double per_round = mode == 0 ? (double)in_flight : mode == 1 ? 1.0 : (double)in_flight + 1.0;
+    const double per_round = mode == 0 ? (double)in_flight : mode == 1 ? 1.0
+                           : mode == 4 ? 4.0 * (double)in_flight : (double)in_flight + 1.0;
     const double ops = (double)grid * 256.0 * (double)work * per_round;
     *rate = ms > 0 ? ops / (ms * 1e-3) : 0.0;
     (void)hipEventDestroy(a);
