@@ -15,6 +15,9 @@ m = 5, omega = 4096), the random-gather sweep, the 512-graph batch, serving on
 a resident R-MAT 21 graph, SpanTree, loop-included paths, node pairs, the
 landmark study and Kemeny's constant of synthetic families.  Each workload
 with a CPU figure times the oracle on the host's cores on a bounded sample.
+The small, mid, large, batched and serving workloads are defined in
+graphgen/workloads.json (graph recipe, preparation, landmark, sample budget,
+blocks and seeds).
 
 Prints one JSON line.
 """
@@ -172,7 +175,7 @@ def oracle_threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
-def cpu_baseline(og, root, omega_full, budget_s=15.0, probe=64):
+def cpu_baseline(og, root, omega_full, budget_s=15.0, probe=64, seed=SEED):
     """The oracle (C, OpenMP over samples) on a bounded sample of the same
     workload: the first n_s samples (Wilson + both absorbed-walk kinds), n_s
     sized from a probe run to take about budget_s; repeated when the whole
@@ -181,14 +184,14 @@ def cpu_baseline(og, root, omega_full, budget_s=15.0, probe=64):
     threads = oracle_threads()
     probe = min(probe, omega_full)
     t = time.perf_counter()
-    native.wilson(og, root, omega_full, SEED, n_samples=probe, want_y1=True, threads=threads)
+    native.wilson(og, root, omega_full, seed, n_samples=probe, want_y1=True, threads=threads)
     dt = time.perf_counter() - t
     n_s = int(min(omega_full, max(probe, probe * budget_s / max(dt, 1e-3))))
     reps, steps, trees, t = 0, 0, 0, time.perf_counter()
     while True:
-        w = native.wilson(og, root, omega_full, SEED, n_samples=n_s, threads=threads)
-        a1 = native.absorbed(og, root, n_s, SEED, 1, omega_total=omega_full, threads=threads)
-        a2 = native.absorbed(og, root, n_s, SEED, 2, omega_total=omega_full, want_y2=False, threads=threads)
+        w = native.wilson(og, root, omega_full, seed, n_samples=n_s, threads=threads)
+        a1 = native.absorbed(og, root, n_s, seed, 1, omega_total=omega_full, threads=threads)
+        a2 = native.absorbed(og, root, n_s, seed, 2, omega_total=omega_full, want_y2=False, threads=threads)
         steps += int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
         trees += n_s
         reps += 1
@@ -197,9 +200,9 @@ def cpu_baseline(og, root, omega_full, budget_s=15.0, probe=64):
             break
     n1 = max(2, min(n_s, n_s // (2 * threads)))
     t1 = time.perf_counter()
-    w = native.wilson(og, root, omega_full, SEED, n_samples=n1, threads=1)
-    a1 = native.absorbed(og, root, n1, SEED, 1, omega_total=omega_full, threads=1)
-    a2 = native.absorbed(og, root, n1, SEED, 2, omega_total=omega_full, want_y2=False, threads=1)
+    w = native.wilson(og, root, omega_full, seed, n_samples=n1, threads=1)
+    a1 = native.absorbed(og, root, n1, seed, 1, omega_total=omega_full, threads=1)
+    a2 = native.absorbed(og, root, n1, seed, 2, omega_total=omega_full, want_y2=False, threads=1)
     steps1 = int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
     dt1 = time.perf_counter() - t1
     return {"value": steps / dt, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
@@ -219,7 +222,7 @@ def _out_tensors(n):
     return out
 
 
-def timed_steps(lap, g, omega, root, steps, warmup, B=64, walks=0):
+def timed_steps(lap, g, omega, root, steps, warmup, B=64, walks=0, seed=SEED):
     """Run warmup + steps plain steps on torch's current stream; time the
     steps between two device synchronisations, with per-kernel HIP-event
     timing (on the streams the kernels run on) over the timed region."""
@@ -227,14 +230,14 @@ def timed_steps(lap, g, omega, root, steps, warmup, B=64, walks=0):
     out = _out_tensors(g.n)
     stream = torch.cuda.current_stream()
     for i in range(warmup):
-        g.estimate(omega, SEED, root, B=B, out=out, stream=stream, walks=walks)
+        g.estimate(omega, seed, root, B=B, out=out, stream=stream, walks=walks)
     torch.cuda.synchronize()
     lap.prof_reset()
     lap.prof_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        g.estimate(omega, SEED, root, B=B, out=out, stream=stream, walks=walks)
+        g.estimate(omega, seed, root, B=B, out=out, stream=stream, walks=walks)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lap.prof_enable(False)
@@ -294,26 +297,28 @@ def request_rate(traffic, kern_ms, gather):
 
 
 # ----------------------------------------------------------------- workloads
-def rmat_graph(lap, gg, scale):
+def workload_graph(lap, gg, name):
+    """The graph of a workload of graphgen/workloads.json, prepared as it says."""
+    w = gg.workload(name)
     t = time.perf_counter()
-    src, dst = gg.rmat(scale, 16, seed=0)
-    g = lap.Graph(1 << scale, src, dst, keep_lcc=True, degree_order=True)
-    log(f"R-MAT {scale} LCC n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
-    return g, src, dst
+    n, src, dst = gg.workload_edges(name)
+    g = lap.Graph(n, src, dst, keep_lcc=w["keep_lcc"], degree_order=w["degree_order"])
+    log(f"{name}: n={g.n} 2m={g.nnz} prepared in {time.perf_counter() - t:.1f} s")
+    return g, n, src, dst
 
 
-def lds_form_rate(lap, g, omega, root, draws, reps=3):
+def lds_form_rate(lap, g, omega, root, draws, reps=3, B=64, seed=SEED):
     """The LDS lane form (graph and state in LDS) on the same samples, against
     the LDS random-read rate of the device (lap_bench_gather mode 4: a sweep of
     lanes and reads in flight per round).  A draw of that form makes about six
     LDS accesses: two row offsets, one column, the state word read and written
     at the node, the target's state word."""
     lds_peak = max(lap.bench_gather(1 << 20, 1 << lg, 4, d) for lg in (14, 16, 18, 20) for d in (1, 4, 16))
-    g.sample_forests(omega, SEED, root, B=64, mode=4)
+    g.sample_forests(omega, seed, root, B=B, mode=4)
     lap.prof_reset()
     lap.prof_enable(True)
     for _ in range(reps):
-        g.sample_forests(omega, SEED, root, B=64, mode=4)
+        g.sample_forests(omega, seed, root, B=B, mode=4)
     lap.prof_enable(False)
     ms, n = lap.prof_read("wilson_lds")
     ms /= max(n, 1)
@@ -323,18 +328,19 @@ def lds_form_rate(lap, g, omega, root, draws, reps=3):
 
 
 def bench_small(lap, gg, steps, warmup, with_cpu, gather):
-    """Small workload: ER(256, 0.05), graph seed 0, resampled until connected,
-    root = max degree, omega = 2^14; accuracy against the dense FP64
-    pseudo-inverse at Philox seed 1 (CPU leg), GPU and CPU rates.  A step
-    takes about 2 ms, so four are timed per headline step."""
-    n, omega = 256, 1 << 14
-    src, dst, _ = gg.erdos_renyi_connected(n, 0.05, 0)
-    g = lap.Graph(n, src, dst)
+    """Small workload (workloads.json "small": ER(256, 0.05), graph seed 0,
+    resampled until connected, root = max degree, omega = 2^14); accuracy
+    against the dense FP64 pseudo-inverse at its Philox seed (CPU leg), GPU
+    and CPU rates.  A step takes about 2 ms, so four are timed per headline
+    step."""
+    w = gg.workload("small")
+    g, n, src, dst = workload_graph(lap, gg, "small")
+    omega, B, seed = w["omega"], w["blocks"], w["philox_seed"]
     root = g.max_deg_node
     reps = 4 * steps
-    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, reps, warmup)
+    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, reps, warmup, B=B, seed=seed)
     kms = kern[wk]["ms_avg"]
-    res = {"workload": "ER(256, 0.05) seed 0 connected, root = max degree, omega = 2^14, Philox seed 1",
+    res = {"workload": gg.describe_workload("small"),
            "s_per_step": dt / reps, "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) * reps / dt,
            "trees_per_s": omega * reps / dt, "wilson_kernel": wk, "wilson_kernel_ms": kms,
            "kernel_ms": {k: v["ms_avg"] for k, v in kern.items()},
@@ -347,7 +353,7 @@ def bench_small(lap, gg, steps, warmup, with_cpu, gather):
     # everything sits in the caches and the generator runs once per draw: the
     # vector ALU issue rate is the roofline that applies
     res["roofline"] = valu_rate(traffic, kms)
-    res["lds_form"] = lds_form_rate(lap, g, omega, root, st["wilson_steps"])
+    res["lds_form"] = lds_form_rate(lap, g, omega, root, st["wilson_steps"], B=B, seed=seed)
     if gather and traffic and "l2" in traffic:
         per = traffic["l2"]["l1_to_l2_read_requests_per_draw"]
         rate = per * st["wilson_steps"] / (kms * 1e-3)
@@ -357,7 +363,7 @@ def bench_small(lap, gg, steps, warmup, with_cpu, gather):
                              "frac_of_4MiB_peak": rate / gather["tiers"]["4MiB"]["peak"]}
     if with_cpu:
         from oracle import csr as ocsr, dense, native
-        og = ocsr.build_csr(n, src, dst)
+        og = ocsr.build_csr(n, src, dst, keep_lcc=w["keep_lcc"], degree_order=w["degree_order"])
         L = dense.laplacian(og)
         t = time.perf_counter()
         Ld = dense.pinv_eigh(L)
@@ -371,7 +377,7 @@ def bench_small(lap, gg, steps, warmup, with_cpu, gather):
         k_gpu = float(out["kemeny"].item())
         rel_c = np.abs(c_gpu - c_true) / c_true
         # the same samples with loop-included paths in place of fresh walks
-        dtl, stl, kernl, _, outl = timed_steps(lap, g, omega, root, reps, warmup, walks=1)
+        dtl, stl, kernl, _, outl = timed_steps(lap, g, omega, root, reps, warmup, B=B, walks=1, seed=seed)
         c_loop = outl["closeness"].cpu().numpy()
         k_loop = float(outl["kemeny"].item())
         rel_l = np.abs(c_loop - c_true) / c_true
@@ -387,30 +393,30 @@ def bench_small(lap, gg, steps, warmup, with_cpu, gather):
             "target": "<= 1e-2 relative (kappa and mean closeness)",
             "routes_agree": float(np.abs(Ld - Ld2).max())}
         # the SpanTree estimators (Alg. 1, Alg. 3) on the same 2^14 Wilson trees
-        sp = g.spantree_estimate(omega, SEED, root, B=64)
+        sp = g.spantree_estimate(omega, seed, root, B=B)
         rel_cs = np.abs(sp["closeness"] - c_true) / c_true
         res["accuracy_vs_dense_pinv"]["spantree_same_trees"] = {
             "kemeny_rel_err": abs(float(sp["kemeny"][0]) - k_true) / k_true,
             "kemeny_z": (float(sp["kemeny"][0]) - k_true) / float(sp["kemeny_se"][0]),
             "closeness_mean_rel_err": float(rel_cs.mean()), "closeness_max_rel_err": float(rel_cs.max())}
-        res["cpu_baseline"] = cpu_baseline(og, root, omega, budget_s=5.0)
+        res["cpu_baseline"] = cpu_baseline(og, root, omega, budget_s=5.0, seed=seed)
         res["cpu_baseline"]["dense_pinv_s"] = {"eigh": t_eigh, "inverse": t_inv}
     g.close()
     return res
 
 
 def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
-    """Mid workload: Barabasi-Albert n = 100,000, m = 5, graph seed 0, root =
-    max degree, omega = 4096 (wave form)."""
-    n, m, omega = 100_000, 5, 4096
-    src, dst = gg.barabasi_albert(n, m, 0)
-    g = lap.Graph(n, src, dst, degree_order=True)
+    """Mid workload (workloads.json "mid": Barabasi-Albert n = 100,000, m = 5,
+    graph seed 0, numbered by decreasing degree, root = max degree, omega =
+    4096; wave form)."""
+    w = gg.workload("mid")
+    g, n, src, dst = workload_graph(lap, gg, "mid")
+    omega, B, seed = w["omega"], w["blocks"], w["philox_seed"]
     root = g.max_deg_node
-    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, steps, warmup)
+    dt, st, kern, wk, out = timed_steps(lap, g, omega, root, steps, warmup, B=B, seed=seed)
     kms = kern[wk]["ms_avg"]
     traffic = measured_traffic("mid")
-    res = {"workload": "Barabasi-Albert n=100000 m=5 numbered by decreasing degree, root = max degree, "
-                       "omega = 4096",
+    res = {"workload": gg.describe_workload("mid"),
            "n": g.n, "nnz": g.nnz, "omega": omega, "s_per_step": dt / steps,
            "walk_steps_per_s": (st["wilson_steps"] + st["absorbed_steps"]) * steps / dt,
            "trees_per_s": omega * steps / dt, "wilson_steps_per_step": st["wilson_steps"],
@@ -421,12 +427,13 @@ def bench_mid(lap, gg, steps, warmup, with_cpu, gather):
            "kemeny": float(out["kemeny"].item()), "kemeny_se": float(out["kemeny_se"].item())}
     if with_cpu:
         from oracle import csr as ocsr
-        res["cpu_baseline"] = cpu_baseline(ocsr.build_csr(n, src, dst, degree_order=True), root, omega,
-                                           budget_s=10.0)
+        res["cpu_baseline"] = cpu_baseline(ocsr.build_csr(n, src, dst, keep_lcc=w["keep_lcc"],
+                                                          degree_order=w["degree_order"]),
+                                           root, omega, budget_s=10.0, seed=seed)
     return res, g, root
 
 
-def hot_vertex_share(g, omega, samples=64):
+def hot_vertex_share(g, omega, samples=64, seed=SEED):
     """What staging the hubs' data in LDS or a cache could serve, from the
     draw counts of `samples` trees: with nodes numbered by decreasing degree
     the hubs' arc records open the arc array and their state words open each
@@ -434,7 +441,7 @@ def hot_vertex_share(g, omega, samples=64):
     arc record lies in the first B bytes is sum_u Y1[u] * frac_u(B) / sum Y1;
     arrivals at u are expected sum over neighbours w of Y1[w] / d_w, and the
     share of arrivals at the first K nodes is their sum over the total."""
-    got = g.sample_forests(min(samples, omega), SEED, -1, B=1, per_sample=False)
+    got = g.sample_forests(min(samples, omega), seed, -1, B=1, per_sample=False)
     y1 = got["Y1"][0].astype(np.float64)
     rp, col, _ = g.csr()
     deg = np.diff(rp).astype(np.float64)
@@ -495,18 +502,23 @@ def bench_gather(lap):
 
 
 def bench_batch(lap, gg, n_jobs, with_cpu):
-    """Many-graph batch: 512 jobs (half ER with average degree in [8, 20],
-    half BA with m in 2..8, n log-uniform in [1000, 200000], omega uniform in
-    [256, 4096], job list seed 2), each estimating closeness and Kemeny's
-    constant, in one persistent launch; against the same jobs run one by one
-    through the plain path (identical counts, so equal accuracy)."""
+    """Many-graph batch (workloads.json "batched": 512 jobs, half ER with
+    average degree in [8, 20], half BA with m in 2..8, n log-uniform in
+    [1000, 200000], omega uniform in [256, 4096], job list seed 2), each
+    estimating closeness and Kemeny's constant, in one persistent launch;
+    against the same jobs run one by one through the plain path (identical
+    counts, so equal accuracy)."""
     import torch
+    wb = gg.workload("batched")
+    n_jobs = n_jobs or wb["jobs"]
     t0 = time.perf_counter()
-    specs = gg.batch_jobs(n_jobs, seed=2)
+    specs = gg.batch_jobs(n_jobs, seed=wb["job_seed"], n_lo=wb["n_range"][0], n_hi=wb["n_range"][1],
+                          omega_lo=wb["omega_range"][0], omega_hi=wb["omega_range"][1])
     jobs = []
     for sp in specs:
         s, d = gg.job_edges(sp)
-        jobs.append(dict(n=sp["n"], src=s, dst=d, keep_lcc=True, root=-1, omega=sp["omega"], seed=1))
+        jobs.append(dict(n=sp["n"], src=s, dst=d, keep_lcc=wb["keep_lcc"], root=-1, omega=sp["omega"],
+                         seed=wb["philox_seed"]))
     log(f"batch: generated {n_jobs} graphs in {time.perf_counter() - t0:.1f} s")
     b = lap.Batch(jobs)
     t_tune = time.perf_counter()
@@ -525,12 +537,12 @@ def bench_batch(lap, gg, n_jobs, with_cpu):
     steps = st["wilson_steps"] + st["absorbed_steps"]
     plain_s = 0.0
     for j, job in enumerate(jobs):
-        g = lap.Graph(job["n"], job["src"], job["dst"], keep_lcc=True)
+        g = lap.Graph(job["n"], job["src"], job["dst"], keep_lcc=job["keep_lcc"])
         out = _out_tensors(g.n)
-        g.estimate(job["omega"], 1, -1, B=1, se=False, out=out)         # warm the workspace
+        g.estimate(job["omega"], job["seed"], -1, B=1, se=False, out=out)         # warm the workspace
         torch.cuda.synchronize()
         t = time.perf_counter()
-        g.estimate(job["omega"], 1, -1, B=1, se=False, out=out)
+        g.estimate(job["omega"], job["seed"], -1, B=1, se=False, out=out)
         torch.cuda.synchronize()
         plain_s += time.perf_counter() - t
         g.close()
@@ -551,12 +563,12 @@ def bench_batch(lap, gg, n_jobs, with_cpu):
         steps_c, trees_c, dt = 0, 0, 0.0
         for j in range(0, n_jobs, 32):
             job = jobs[j]
-            og = ocsr.build_csr(job["n"], job["src"], job["dst"], keep_lcc=True)
+            og = ocsr.build_csr(job["n"], job["src"], job["dst"], keep_lcc=job["keep_lcc"])
             root = ocsr.landmark(og)
             tt = time.perf_counter()
-            w = native.wilson(og, root, job["omega"], 1, threads=threads)
-            a1 = native.absorbed(og, root, job["omega"], 1, 1, threads=threads)
-            a2 = native.absorbed(og, root, job["omega"], 1, 2, want_y2=False, threads=threads)
+            w = native.wilson(og, root, job["omega"], job["seed"], threads=threads)
+            a1 = native.absorbed(og, root, job["omega"], job["seed"], 1, threads=threads)
+            a2 = native.absorbed(og, root, job["omega"], job["seed"], 2, want_y2=False, threads=threads)
             dt += time.perf_counter() - tt      # graph preparation untimed
             steps_c += int(w["y1"].sum() + a1["len"].sum() + a2["len"].sum())
             trees_c += job["omega"]
@@ -616,19 +628,23 @@ def _serial(lap, srv, qs, qid0):
     return time.perf_counter() - t0, bad
 
 
-def bench_serve(lap, gg, n_queries, with_cpu, repeats=3):
-    """Serving: resident R-MAT scale-21 graph (edge factor 16, a/b/c/d =
+def bench_serve(lap, gg, n_queries, with_cpu):
+    """Serving (workloads.json "serving"): resident R-MAT scale-21 graph (edge factor 16, a/b/c/d =
     .57/.19/.19/.05, symmetrised, self-loops and duplicates dropped, largest
     component); Poisson arrivals mixing single-node closeness (64..1024 walks,
     log-uniform), pairwise resistance (1024 walk pairs) and Kemeny (256
     samples) in proportions 45/45/10.  Saturation throughput is measured with
     every query submitted at once; latency percentiles (overall and per query
     kind) at 50% and 80% of it, the 80% run repeated on the same server."""
-    g, src, dst = rmat_graph(lap, gg, 21)
+    w = gg.workload("serving")
+    n_queries = n_queries or w["queries"]
+    g, n_graph, src, dst = workload_graph(lap, gg, "serving")
     if not with_cpu:
         del src, dst
-    srv = lap.Server(g, seed=1, global_samples=256)
-    qs = gg.query_stream(g.n, n_queries, qps=1.0, seed=3)
+    srv = lap.Server(g, seed=w["server_seed"], global_samples=w["global_samples"])
+    mix = dict(mix=tuple(w["mix"]), ecc_budget=tuple(w["closeness_walks"]), res_pairs=w["resistance_pairs"],
+               kemeny_samples=w["kemeny_samples"])
+    qs = gg.query_stream(g.n, n_queries, qps=1.0, seed=w["saturation_stream_seed"], **mix)
     for q in qs:
         q["t"] = 0.0
     out_sat, wall = _replay(lap, srv, qs, 0)
@@ -637,16 +653,18 @@ def bench_serve(lap, gg, n_queries, with_cpu, repeats=3):
     n_serial = min(n_queries, 100)
     wall_serial, bad_serial = _serial(lap, srv, qs[:n_serial], 10_000_000)
     log(f"serve: one query at a time {n_serial / wall_serial:.1f} queries/s")
-    res = {"workload": "R-MAT scale 21 LCC (numbered by decreasing degree) resident; Poisson mix 45% closeness (64-1024 walks), "
-                       "45% resistance (1024 walk pairs), 10% Kemeny (256 samples)",
+    res = {"workload": gg.describe_workload("serving") + ", resident; Poisson mix "
+                       f"{w['mix'][0]:.0%} closeness ({w['closeness_walks'][0]}-{w['closeness_walks'][1]} walks), "
+                       f"{w['mix'][1]:.0%} resistance ({w['resistance_pairs']} walk pairs), "
+                       f"{w['mix'][2]:.0%} Kemeny ({w['kemeny_samples']} samples)",
            "n": g.n, "nnz": g.nnz, "queries": n_queries, "saturation_qps": sat,
            "closed_loop": _latency_summary(out_sat),
            "errors": int(sum(r["status"] != 0 for r in out_sat)) + int(bad_serial),
            "one_at_a_time_qps": n_serial / wall_serial,
            "speedup_served_vs_one_at_a_time": sat / (n_serial / wall_serial), "runs": []}
-    loads = [0.5] + [0.8] * repeats
-    for k, frac in enumerate(loads):
-        qs = gg.query_stream(g.n, n_queries, qps=frac * sat, seed=4 + min(k, 1))
+    for frac, stream_seed in zip(w["loads"], w["load_stream_seeds"]):
+        k = len(res["runs"])
+        qs = gg.query_stream(g.n, n_queries, qps=frac * sat, seed=stream_seed, **mix)
         out, wall = _replay(lap, srv, qs, (k + 1) * 1_000_000)
         r = {"offered_qps": frac * sat, "load": frac, "achieved_qps": n_queries / wall}
         r.update(_latency_summary(out))
@@ -656,32 +674,33 @@ def bench_serve(lap, gg, n_queries, with_cpu, repeats=3):
     res["p99_80pct_spread"] = (max(p99s) - min(p99s)) / min(p99s)
     srv.close()
     if with_cpu:
-        res["cpu_baseline"] = serve_cpu(gg, g, src, dst)
+        res["cpu_baseline"] = serve_cpu(gg, w, n_graph, src, dst, mix)
     g.close()
     return res
 
 
-def serve_cpu(gg, g, src, dst, budget_s=12.0):
+def serve_cpu(gg, w, n_graph, src, dst, mix, budget_s=12.0):
     """The oracle answering the query stream's first queries one after another
     (closeness and resistance walks on one thread, Kemeny samples on all
     cores), as a reference for the served latencies."""
     from oracle import csr as ocsr, native
-    og = ocsr.build_csr(1 << 21, src, dst, keep_lcc=True, degree_order=True)
+    og = ocsr.build_csr(n_graph, src, dst, keep_lcc=w["keep_lcc"], degree_order=w["degree_order"])
     root = ocsr.landmark(og)
     threads = oracle_threads()
-    qs = gg.query_stream(og.n, 200, qps=1.0, seed=3)
+    sd = w["server_seed"]
+    qs = gg.query_stream(og.n, 200, qps=1.0, seed=w["saturation_stream_seed"], **mix)
     lat = {0: [], 1: [], 2: []}
     t_all = time.perf_counter()
     for q in qs:
         t = time.perf_counter()
         if q["kind"] == 0:
-            native.query_walks(og, root, 1, q["qid"], q["u"], 0, q["u"], q["u"], q["budget"])
+            native.query_walks(og, root, sd, q["qid"], q["u"], 0, q["u"], q["u"], q["budget"])
         elif q["kind"] == 1:
-            native.query_walks(og, root, 1, q["qid"], q["u"], 0, q["u"], q["w"], q["budget"])
-            native.query_walks(og, root, 1, q["qid"], q["w"], 1, q["w"], q["u"], q["budget"])
+            native.query_walks(og, root, sd, q["qid"], q["u"], 0, q["u"], q["w"], q["budget"])
+            native.query_walks(og, root, sd, q["qid"], q["w"], 1, q["w"], q["u"], q["budget"])
         else:
-            native.wilson(og, root, q["budget"], 1, qid=q["qid"], threads=threads)
-            native.absorbed(og, root, q["budget"], 1, 2, qid=q["qid"], want_y2=False, threads=threads)
+            native.wilson(og, root, q["budget"], sd, qid=q["qid"], threads=threads)
+            native.absorbed(og, root, q["budget"], sd, 2, qid=q["qid"], want_y2=False, threads=threads)
         lat[q["kind"]].append(time.perf_counter() - t)
         if time.perf_counter() - t_all > budget_s:
             break
@@ -887,10 +906,10 @@ def main():
     ap.add_argument("--only", default="", help="comma-separated sections to run (default: all): " +
                                                ",".join(SECTIONS))
     ap.add_argument("--skip", default="", help="comma-separated sections to leave out")
-    ap.add_argument("--batch-jobs", type=int, default=512)
+    ap.add_argument("--batch-jobs", type=int, default=0, help="jobs of the batch (0: the workload's 512)")
     ap.add_argument("--kc-n", type=int, default=100_000)
     ap.add_argument("--kc-er-omega", type=int, default=16384)
-    ap.add_argument("--serve-queries", type=int, default=2000)
+    ap.add_argument("--serve-queries", type=int, default=0, help="queries per serving run (0: the workload's 2000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB (counter calibration) and exit")
     ap.add_argument("--write-traffic", metavar="DIR",
@@ -935,18 +954,17 @@ def main():
         log("random-gather sweep")
         gather = bench_gather(lap)
     if "large" in only:
-        g, src, dst = rmat_graph(lap, gg, 22)
-        omega = 512
+        wl = gg.workload("large")
+        g, n_large, src, dst = workload_graph(lap, gg, "large")
+        omega, B, seed = wl["omega"], wl["blocks"], wl["philox_seed"]
         log(f"large: {args.warmup} warm-up + {args.steps} timed steps")
-        dt, st, kern, wk, out = timed_steps(lap, g, omega, -1, args.steps, args.warmup)
+        dt, st, kern, wk, out = timed_steps(lap, g, omega, -1, args.steps, args.warmup, B=B, seed=seed)
         kms = kern[wk]["ms_avg"]
         traffic = measured_traffic("large")
         res.update({
             "value": (st["wilson_steps"] + st["absorbed_steps"]) * args.steps / dt,
             "ms_per_step": dt * 1e3 / args.steps,
-            "config": {"workload": "plain LEWalk closeness + Kemeny: R-MAT scale 22 (edge factor 16, "
-                                   "a/b/c/d .57/.19/.19/.05) symmetrised, largest component numbered by "
-                                   "decreasing degree, root = max degree, omega = 512 trees, B = 64, Philox seed 1",
+            "config": {"workload": "plain LEWalk closeness + Kemeny: " + gg.describe_workload("large"),
                        "n": g.n, "nnz": g.nnz, "omega": omega, "wilson_kernel": TRAFFIC["large"]["kernel"]},
             "trees_per_s": omega * args.steps / dt,
             "wilson_steps_per_step": st["wilson_steps"], "absorbed_steps_per_step": st["absorbed_steps"],
@@ -962,19 +980,19 @@ def main():
         root = g.max_deg_node
         # the same step with the walk counts from the loop-included paths of
         # the same Wilson samples (Sec. 3.4): after the trees, not beside them
-        dtl, stl, kernl, _, outl = timed_steps(lap, g, omega, -1, 2, 1, walks=1)
+        dtl, stl, kernl, _, outl = timed_steps(lap, g, omega, -1, 2, 1, B=B, walks=1, seed=seed)
         res["large_loop_included"] = {
             "s_per_step": dtl / 2, "kernel_ms": {k: v["ms_avg"] for k, v in kernl.items()},
             "path_steps_per_step": stl["absorbed_steps"],
             "kemeny": float(outl["kemeny"].item()), "kemeny_se": float(outl["kemeny_se"].item()),
             "trace_Ldagger": float(outl["trace"].item())}
-        res["hot_vertex_share"] = hot_vertex_share(g, omega)
+        res["hot_vertex_share"] = hot_vertex_share(g, omega, seed=seed)
         g.close()
         if with_cpu:
             log("large: cpu baseline (oracle)")
             from oracle import csr as ocsr
-            og = ocsr.build_csr(1 << 22, src, dst, keep_lcc=True, degree_order=True)
-            res["cpu_baseline"] = cpu_baseline(og, root, omega, budget_s=15.0, probe=16)
+            og = ocsr.build_csr(n_large, src, dst, keep_lcc=wl["keep_lcc"], degree_order=wl["degree_order"])
+            res["cpu_baseline"] = cpu_baseline(og, root, omega, budget_s=15.0, probe=16, seed=seed)
             del og
         del src, dst
     if "small" in only:

@@ -9,6 +9,7 @@ library and once in ``oracle/``.
 from __future__ import annotations
 
 import ctypes
+import json
 import math
 import os
 import subprocess
@@ -181,6 +182,59 @@ def grid(rows, cols):
 
 
 # ------------------------------------------------------------- workload recipes
+# The benchmark's workloads (graph recipe, preparation, landmark, sample
+# budget, blocks, seeds) live in workloads.json beside this file.
+_WORKLOADS = os.path.join(_HERE, "workloads.json")
+
+
+def workload(name: str) -> dict:
+    """Parameters of a benchmark workload: small, mid, large, batched, serving."""
+    with open(_WORKLOADS) as f:
+        table = json.load(f)
+    if name not in table:
+        raise KeyError(f"unknown workload {name!r}; known: {sorted(table)}")
+    return table[name]
+
+
+def workload_edges(name: str):
+    """(n, src, dst) of a graph workload, built from its recipe (before the
+    largest-component and numbering steps, which the graph builder applies)."""
+    g = workload(name)["graph"]
+    fam = g["family"]
+    if fam == "erdos_renyi_connected":
+        s, d, _ = erdos_renyi_connected(g["n"], g["p"], g["seed"])
+        return g["n"], s, d
+    if fam == "barabasi_albert":
+        s, d = barabasi_albert(g["n"], g["m"], g["seed"])
+        return g["n"], s, d
+    if fam == "rmat":
+        s, d = rmat(g["scale"], g["edge_factor"], g["a"], g["b"], g["c"], seed=g["seed"])
+        return 1 << g["scale"], s, d
+    raise ValueError(f"unknown graph family {fam!r}")
+
+
+def describe_workload(name: str) -> str:
+    """One line naming a graph workload's recipe and parameters."""
+    w = workload(name)
+    g = w["graph"]
+    fam = g["family"]
+    if fam == "erdos_renyi_connected":
+        text = f"ER({g['n']}, {g['p']}) seed {g['seed']} connected"
+    elif fam == "barabasi_albert":
+        text = f"Barabasi-Albert n={g['n']} m={g['m']}"
+    else:
+        d = round(1.0 - g["a"] - g["b"] - g["c"], 6)
+        text = (f"R-MAT scale {g['scale']} (edge factor {g['edge_factor']}, a/b/c/d {g['a']}/{g['b']}/{g['c']}/{d}) "
+                "symmetrised")
+    if w.get("keep_lcc"):
+        text += ", largest component"
+    if w.get("degree_order"):
+        text += " numbered by decreasing degree"
+    if "omega" in w:
+        text += f", root = max degree, omega = {w['omega']}, B = {w['blocks']}, Philox seed {w['philox_seed']}"
+    return text
+
+
 def batch_jobs(n_graphs: int = 512, seed: int = 2, n_lo: int = 1000, n_hi: int = 200_000,
                omega_lo: int = 256, omega_hi: int = 4096):
     """Job list for the many-graph batch: half ER (average degree uniform in

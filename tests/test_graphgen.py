@@ -76,3 +76,31 @@ def test_hyperbolic_degree_tail():
         assert 7.0 < deg.mean() < 13.0
         tails.append(np.sort(deg)[-n // 1000:].mean())
     assert tails[0] > 1.5 * tails[1]
+
+
+def test_workload_table():
+    """Every benchmark workload is in the table; the graph recipes build the
+    edge lists the generators give for the same parameters, and the
+    descriptions name them."""
+    for name in ("small", "mid", "large", "batched", "serving"):
+        w = gg.workload(name)
+        assert w.get("philox_seed", 1) == 1
+    with pytest.raises(KeyError):
+        gg.workload("no such workload")
+    n, s, d = gg.workload_edges("small")
+    s2, d2, _ = gg.erdos_renyi_connected(256, 0.05, 0)
+    assert n == 256 and np.array_equal(s, s2) and np.array_equal(d, d2)
+    n, s, d = gg.workload_edges("mid")
+    s2, d2 = gg.barabasi_albert(100_000, 5, 0)
+    assert n == 100_000 and np.array_equal(s, s2) and np.array_equal(d, d2)
+    assert gg.workload("large")["graph"]["scale"] == 22 and gg.workload("serving")["graph"]["scale"] == 21
+    assert "ER(256, 0.05)" in gg.describe_workload("small")
+    assert "Barabasi-Albert n=100000 m=5" in gg.describe_workload("mid")
+    text = gg.describe_workload("large")
+    assert "R-MAT scale 22" in text and "0.57/0.19/0.19/0.05" in text and "largest component" in text
+    b = gg.workload("batched")
+    jobs = gg.batch_jobs(b["jobs"], seed=b["job_seed"], n_lo=b["n_range"][0], n_hi=b["n_range"][1],
+                         omega_lo=b["omega_range"][0], omega_hi=b["omega_range"][1])
+    assert jobs == gg.batch_jobs(512)
+    sv = gg.workload("serving")
+    assert len(sv["loads"]) == len(sv["load_stream_seeds"]) and abs(sum(sv["mix"]) - 1.0) < 1e-12
