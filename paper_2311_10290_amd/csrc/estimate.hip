@@ -6,8 +6,8 @@
 // visit of that node and one unit of length; the arrival at v ends the walk.
 //
 // Assembly (Alg. 2 last loop, the closeness formula of Sec. 2, Alg. 4 update)
-// from exact integer counts, dividing once in FP64:
-//   S_b    = sum_w Y2_b[w] / d_w                         per block b and overall
+// from exact integer counts in FP64:
+//   S_b    = sum_w Y2_b[w] / d_w  per block b,  S = sum_b S_b
 //   diag_u = (Y1[u] - 2 Y2[u]) / (omega d_u) + S / (omega n)
 //   c_u    = (n-1) / (Tr + n diag_u),  Tr = sum_u diag_u
 //   kappa  = (sum_i y1_i - sum_i len_i) / omega
@@ -55,15 +55,29 @@ hipError_t launch_absorbed(const AbsorbedParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
+// 16-byte stores over the 16-byte aligned body; the word before it (when the
+// buffer starts 8 bytes past a 16-byte boundary) and the word after it (odd
+// length) are stored by the first thread.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
 __global__ void fill_u64_kernel(uint64_t *dst, uint64_t value, int64_t n) {
+    const int64_t head = ((uintptr_t)dst & 15) ? 1 : 0;
+    const int64_t pairs = (n - head) / 2;
+    u64x2 *body = reinterpret_cast<u64x2 *>(dst + head);
+    const u64x2 w = {value, value};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = value;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pairs; i += stride) body[i] = w;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (head) dst[0] = value;
+        if (head + 2 * pairs < n) dst[n - 1] = value;
+    }
 }
 
 hipError_t launch_fill_u64(uint64_t *dst, uint64_t value, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t grid = (n + 255) / 256;
-    if (grid > 4096) grid = 4096;
+    int64_t grid = (n / 2 + 255) / 256;
+    if (grid < 1) grid = 1;
+    if (grid > 65536) grid = 65536;
     hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)grid), dim3(256), 0, s, dst, value, n);
     return hipGetLastError();
 }
@@ -88,29 +102,23 @@ constexpr int kAsmBS = 256;
 
 __device__ __forceinline__ double deg_of(const uint64_t *nbr, int64_t u) { return (double)nbr_deg(nbr[u]); }
 
-// partial[b * n_parts + part] = sum over this part's nodes of Y2_b[w] / d_w
-// (b == B: all blocks together)
+// partial[b * n_parts + part] = sum over this part's nodes of Y2_b[w] / d_w.
+// Workgroups of one part for consecutive blocks are launched together, so the
+// part's degrees are read from L2 after the first.
 __global__ __launch_bounds__(kAsmBS) void y2_sums_kernel(AssembleParams p) {
     __shared__ double sh[kAsmBS];
-    const int b = blockIdx.y;
+    const int b = blockIdx.x;
     const int64_t per = (p.n + p.n_parts - 1) / p.n_parts;
-    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(p.n, lo + per);
+    const int64_t lo = (int64_t)blockIdx.y * per, hi = min(p.n, lo + per);
+    const unsigned long long *y2 = p.y2 + (int64_t)b * p.n;
     double acc = 0.0;
-    for (int64_t w = lo + threadIdx.x; w < hi; w += kAsmBS) {
-        if (w == p.root) continue;
-        unsigned long long c;
-        if (b < p.n_blocks) {
-            c = p.y2[(int64_t)b * p.n + w];
-        } else {
-            c = 0;
-            for (int q = 0; q < p.n_blocks; ++q) c += p.y2[(int64_t)q * p.n + w];
-        }
-        acc += (double)c / deg_of(p.nbr, w);
-    }
+    for (int64_t w = lo + threadIdx.x; w < hi; w += kAsmBS)
+        if (w != p.root) acc += (double)y2[w] / deg_of(p.nbr, w);
     const double s = block_sum<kAsmBS>(acc, sh);
-    if (threadIdx.x == 0) p.partial[(int64_t)b * p.n_parts + blockIdx.x] = s;
+    if (threadIdx.x == 0) p.partial[(int64_t)b * p.n_parts + blockIdx.y] = s;
 }
 
+// sums[b] = S_b, one workgroup per block
 __global__ __launch_bounds__(kAsmBS) void y2_sums_final_kernel(AssembleParams p) {
     __shared__ double sh[kAsmBS];
     const int b = blockIdx.x;
@@ -120,6 +128,15 @@ __global__ __launch_bounds__(kAsmBS) void y2_sums_final_kernel(AssembleParams p)
     if (threadIdx.x == 0) p.sums[b] = s;
 }
 
+// sums[B] = S = sum_b S_b (every visit belongs to exactly one block)
+__global__ __launch_bounds__(kAsmBS) void y2_total_kernel(AssembleParams p) {
+    __shared__ double sh[kAsmBS];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < p.n_blocks; b += kAsmBS) acc += p.sums[b];
+    const double s = block_sum<kAsmBS>(acc, sh);
+    if (threadIdx.x == 0) p.sums[p.n_blocks] = s;
+}
+
 __device__ __forceinline__ int64_t block_count(int64_t omega, int32_t B, int32_t b) {
     // number of i in [0, omega) with floor(i*B/omega) == b
     const int64_t lo = ((int64_t)b * omega + B - 1) / B;
@@ -127,53 +144,74 @@ __device__ __forceinline__ int64_t block_count(int64_t omega, int32_t B, int32_t
     return hi - lo;
 }
 
+// Per-block constants of diag_kernel: sample count omega_b, 1/omega_b and
+// S_b/(omega_b n), in LDS when there are at most kAsmTab blocks.
+constexpr int kAsmTab = 1024;
+
+struct BlockConst {
+    unsigned long long cnt;
+    double scale, glob;
+};
+
+__device__ __forceinline__ BlockConst block_const(const AssembleParams &p, int b, double nn) {
+    const int64_t ob = block_count(p.omega, p.n_blocks, b);
+    return BlockConst{(unsigned long long)ob, 1.0 / (double)ob, p.sums[b] / ((double)ob * nn)};
+}
+
+// diag_u, its batch-means standard error and (L_v^-1)_uu; per-part sums of
+// diag_u for the trace.  The spread over blocks is accumulated as sums of
+// v_b - v_0 and its square (shifted data), which needs no division per block.
+template <bool TAB>
 __global__ __launch_bounds__(kAsmBS) void diag_kernel(AssembleParams p) {
     __shared__ double sh[kAsmBS];
+    __shared__ BlockConst tab[TAB ? kAsmTab : 1];
+    const int B = p.n_blocks;
+    const double nn = (double)p.n;
+    if (TAB) {
+        for (int b = threadIdx.x; b < B; b += kAsmBS) tab[b] = block_const(p, b, nn);
+        __syncthreads();
+    }
+    auto bc = [&](int b) -> BlockConst { return TAB ? tab[b] : block_const(p, b, nn); };
     const int64_t per = (p.n + p.n_parts - 1) / p.n_parts;
     const int64_t lo = (int64_t)blockIdx.x * per, hi = min(p.n, lo + per);
-    const double nn = (double)p.n;
+    const double om = (double)p.omega;
     double tr = 0.0;
     for (int64_t u = lo + threadIdx.x; u < hi; u += kAsmBS) {
-        double diag, se = 0.0, lv = 0.0;
+        double diag, lv = 0.0, k = 0.0, s1 = 0.0, s2 = 0.0;
         if (u == p.root) {
-            diag = p.sums[p.n_blocks] / ((double)p.omega * nn);
-            if (p.n_blocks > 1) {
-                double m = 0.0, m2 = 0.0;
-                for (int b = 0; b < p.n_blocks; ++b) {
-                    const double ob = (double)block_count(p.omega, p.n_blocks, b);
-                    const double v = p.sums[b] / (ob * nn);
-                    const double d = v - m;
-                    m += d / (b + 1);
-                    m2 += d * (v - m);
-                }
-                se = sqrt(m2 / (p.n_blocks - 1)) / sqrt((double)p.n_blocks);
+            diag = p.sums[B] / (om * nn);
+            for (int b = 0; b < B; ++b) {
+                const double v = bc(b).glob;
+                if (b == 0) k = v;
+                s1 += v - k;
+                s2 += (v - k) * (v - k);
             }
         } else {
             const double du = deg_of(p.nbr, u);
+            const double inv_du = 1.0 / du;
             unsigned long long a1 = 0, a2 = 0;
-            double m = 0.0, m2 = 0.0;
-            for (int b = 0; b < p.n_blocks; ++b) {
+#pragma unroll 8
+            for (int b = 0; b < B; ++b) {
+                const BlockConst c = bc(b);
                 // counts hold draws beyond the first; add the one-per-sample baseline
-                const unsigned long long c1 =
-                    p.y1[(int64_t)b * p.n + u] + (unsigned long long)block_count(p.omega, p.n_blocks, b);
+                const unsigned long long c1 = p.y1[(int64_t)b * p.n + u] + c.cnt;
                 const unsigned long long c2 = p.y2[(int64_t)b * p.n + u];
                 a1 += c1;
                 a2 += c2;
-                if (p.n_blocks > 1) {
-                    const double ob = (double)block_count(p.omega, p.n_blocks, b);
-                    const double v = ((double)c1 - 2.0 * (double)c2) / (ob * du) + p.sums[b] / (ob * nn);
-                    const double d = v - m;
-                    m += d / (b + 1);
-                    m2 += d * (v - m);
-                }
+                const double v = ((double)c1 - 2.0 * (double)c2) * (c.scale * inv_du) + c.glob;
+                if (b == 0) k = v;
+                s1 += v - k;
+                s2 += (v - k) * (v - k);
             }
-            const double om = (double)p.omega;
-            diag = ((double)a1 - 2.0 * (double)a2) / (om * du) + p.sums[p.n_blocks] / (om * nn);
+            diag = ((double)a1 - 2.0 * (double)a2) / (om * du) + p.sums[B] / (om * nn);
             lv = (double)a1 / (om * du);
-            if (p.n_blocks > 1) se = sqrt(m2 / (p.n_blocks - 1)) / sqrt((double)p.n_blocks);
         }
         if (p.diag) p.diag[u] = diag;
-        if (p.diag_se) p.diag_se[u] = (p.n_blocks > 1) ? se : __builtin_nan("");
+        if (p.diag_se) {
+            double se = __builtin_nan("");
+            if (B > 1) se = sqrt(fmax(0.0, (s2 - s1 * s1 / (double)B) / (double)(B - 1)) / (double)B);
+            p.diag_se[u] = se;
+        }
         if (p.lv_diag) p.lv_diag[u] = lv;
         tr += diag;
     }
@@ -204,10 +242,14 @@ __global__ __launch_bounds__(kAsmBS) void closeness_kernel(AssembleParams p, con
 }
 
 hipError_t launch_assemble_diag(const AssembleParams &p, hipStream_t s) {
-    hipLaunchKernelGGL(y2_sums_kernel, dim3((unsigned)p.n_parts, (unsigned)(p.n_blocks + 1)), dim3(kAsmBS),
-                       0, s, p);
-    hipLaunchKernelGGL(y2_sums_final_kernel, dim3((unsigned)(p.n_blocks + 1)), dim3(kAsmBS), 0, s, p);
-    hipLaunchKernelGGL(diag_kernel, dim3((unsigned)p.n_parts), dim3(kAsmBS), 0, s, p);
+    if (p.n_parts < 1 || p.n_parts > 65535 || p.n_blocks < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(y2_sums_kernel, dim3((unsigned)p.n_blocks, (unsigned)p.n_parts), dim3(kAsmBS), 0, s, p);
+    hipLaunchKernelGGL(y2_sums_final_kernel, dim3((unsigned)p.n_blocks), dim3(kAsmBS), 0, s, p);
+    hipLaunchKernelGGL(y2_total_kernel, dim3(1), dim3(kAsmBS), 0, s, p);
+    if (p.n_blocks <= kAsmTab)
+        hipLaunchKernelGGL(diag_kernel<true>, dim3((unsigned)p.n_parts), dim3(kAsmBS), 0, s, p);
+    else
+        hipLaunchKernelGGL(diag_kernel<false>, dim3((unsigned)p.n_parts), dim3(kAsmBS), 0, s, p);
     hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(kAsmBS), 0, s, p);
     if (p.closeness || p.rw_betweenness) {
         int64_t grid = (p.n + kAsmBS - 1) / kAsmBS;
