@@ -57,6 +57,15 @@ def test_host_side_rejections():
     assert "connected components" in msg
 
 
+def test_degree_limit_rejected_before_device_work():
+    """A star whose centre has 2^24 neighbours: the degree field of the
+    adjacency record holds 24 bits, so the build stops with LAP_ERANGE."""
+    from paper_2311_10290_amd import _capi as C
+    d = 1 << 24
+    rc, msg = _build(d + 1, np.zeros(d, np.int32), np.arange(1, d + 1, dtype=np.int32))
+    assert rc == C.LAP_ERANGE and "2^24" in msg
+
+
 def test_null_handle_rejections():
     from paper_2311_10290_amd import _capi as C, load_library
     lib = load_library()
