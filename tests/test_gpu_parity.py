@@ -175,6 +175,31 @@ def test_estimates_match_oracle_assembly_and_dense_truth():
     assert abs(est["kemeny"][0] - dense.kemeny_spectral(og)) < 3 * est["kemeny_se"][0]
 
 
+@pytest.mark.parametrize("B", [1, 2, 1024, 1025, 3000])
+def test_assembly_over_block_counts(B):
+    """The assembly keeps per-block constants in LDS for up to 1024 blocks and
+    computes them per block beyond; one sample per block at B = omega."""
+    n, s, d = er256_edges()
+    og, hg = both(n, s, d)
+    root = csr.landmark(og)
+    omega = 3000
+    log(f"estimate er256 B={B}")
+    est = hg.estimate(omega, 6, root, B=B, lv=True)
+    exp = _oracle_counts(og, root, omega, 6, B=B)
+    diag, se = estimators.diag_ldagger_blocks(exp["Y1"], exp["Y2"], omega, og.deg)
+    c, tr = estimators.closeness(diag)
+    np.testing.assert_allclose(est["diag"], diag, rtol=1e-12, atol=1e-15)
+    if B > 1:
+        np.testing.assert_allclose(est["diag_se"], se, rtol=1e-9, atol=1e-15)
+    else:
+        assert np.isnan(est["diag_se"]).all()
+    np.testing.assert_allclose(est["closeness"], c, rtol=1e-12)
+    np.testing.assert_allclose(est["trace"][0], tr, rtol=1e-12)
+    lv = exp["Y1"].sum(0) / (omega * og.deg)
+    lv[root] = 0.0
+    np.testing.assert_allclose(est["lv_diag"], lv, rtol=1e-12)
+
+
 @pytest.mark.parametrize("mode,group,pool", [(0, 0, 0), (2, 0, 7), (3, 4, 0), (1, 0, 300)])
 def test_loop_included_estimates_match_oracle(mode, group, pool):
     """lap_estimate with the walk counts from the loop-included paths of the
