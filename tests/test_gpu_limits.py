@@ -1,6 +1,7 @@
 """Parity at the sampler's documented limits, through the C ABI: node degree
-below 2^24 (the adjacency record's degree field) and at most 2^21 - 1 draws
-at one node in one sample (the state word's count field).
+below 2^24 (the adjacency record's degree field), at most 2^21 - 1 draws at
+one node in one sample (the state word's count field), and sample indices
+below 2^56 with the key words at their largest values.
 
   - Double star: nodes 0 and 1 joined to each other and to every other node
     of 2^24, so both have degree 2^24 - 1 and each draw there maps a 64-bit
@@ -81,3 +82,35 @@ def test_star_draw_limit_reported_and_samples_below_it_exact():
                                 timeout_s=300)
         _same(got, dict(Y1=w["Y1"], y1=w["y1"], next=w["next"], draws=w["draws"]), ["Y1", "y1", "next", "draws"])
     hg.close()
+
+
+def test_extreme_keys_and_sample_indices_bit_exact():
+    """The last 64 sample and walk indices below 2^56 (the counter field the
+    keying leaves them) with the largest seed and stream id and a query id
+    near 2^64: counts, kept trees and walk lengths equal the oracle's in
+    every sampler form; a run of 2^56 samples is refused."""
+    from paper_2311_10290_amd import LapError
+    from tests.gpu_common import both, er256_edges
+    n, s, d = er256_edges()
+    og, hg = both(n, s, d)
+    root = csr.landmark(og)
+    total = (1 << 56) - 1
+    begin = total - 64
+    seed, stream, qid = (1 << 64) - 1, (1 << 32) - 1, (1 << 64) - 2
+    keep = [begin, total - 1]
+    w = native.wilson(og, root, total, seed, stream=stream, qid=qid, sample_begin=begin, n_samples=64, B=4,
+                      keep=keep)
+    a1 = native.absorbed(og, root, 64, seed, 1, stream=stream, qid=qid, walk_begin=begin, omega_total=total, B=4)
+    a2 = native.absorbed(og, root, 64, seed, 2, stream=stream, qid=qid, walk_begin=begin, omega_total=total,
+                         want_y2=False)
+    exp = dict(Y1=w["Y1"], y1=w["y1"], next=w["next"], draws=w["draws"], Y2=a1["Y2"], len_uniform=a1["len"],
+               len_pi=a2["len"])
+    assert exp["Y1"][:3].sum() == 0 and exp["Y1"][3].sum() > 0     # every sample falls in the last block
+    for mode in (1, 2, 3, 4):
+        log(f"extreme keys: mode {mode}")
+        got = hg.sample_forests(64, seed, root, y2=True, y2_pi=True, B=4, keep=keep, sample_begin=begin,
+                                n_total=total, mode=mode, stream_id=stream, qid=qid)
+        _same(got, exp, ["Y1", "y1", "next", "draws", "Y2", "len_uniform", "len_pi"])
+    with pytest.raises(LapError) as ei:
+        hg.sample_forests(1, seed, root, n_total=1 << 56)
+    assert ei.value.code == -1 and "2^56" in str(ei.value)
