@@ -64,6 +64,35 @@ def test_batch_bit_exact_eager():
         assert st["trees"] == sum(j["omega"] for j in jobs)
 
 
+def test_batch_with_degenerate_jobs():
+    """A single-node graph (no edges: every count and estimate is zero), a
+    single edge, a star with one sample and two ordinary jobs share one
+    launch, eagerly and from the captured graph."""
+    from paper_2311_10290_amd import Batch
+    s5, d5 = gg.barabasi_albert(700, 3, 41)
+    s6, d6 = gg.erdos_renyi(400, 0.03, 42)
+    star = np.arange(1, 40, dtype=np.int32)
+    jobs = [dict(n=1, src=np.zeros(0, np.int32), dst=np.zeros(0, np.int32), keep_lcc=True, root=-1, omega=5, seed=2,
+                 stream_id=0, qid=0),
+            dict(n=2, src=np.array([0], np.int32), dst=np.array([1], np.int32), keep_lcc=True, root=-1, omega=7,
+                 seed=3, stream_id=1, qid=0),
+            dict(n=700, src=s5, dst=d5, keep_lcc=True, root=-1, omega=129, seed=1, stream_id=0, qid=0),
+            dict(n=40, src=np.zeros(39, np.int32), dst=star, keep_lcc=True, root=5, omega=1, seed=4, stream_id=0,
+                 qid=0),
+            dict(n=400, src=s6, dst=d6, keep_lcc=True, root=-1, omega=64, seed=2, stream_id=1, qid=0)]
+    b = Batch(jobs)
+    for use_graph in (False, True):
+        log(f"batch with degenerate jobs, graph {use_graph}")
+        b.run(Batch.tuning(pool=3, chunk_nodes=256, use_graph=use_graph))
+        r = b.result(0)
+        assert b.info[0]["n"] == 1
+        for k in ("Y1", "Y2", "y1", "len_uniform", "len_pi", "diag", "closeness", "trace", "kemeny"):
+            assert not np.any(r[k]), k
+        for j in range(1, len(jobs)):
+            _check_job(b, jobs, j)
+        assert b.stats()["trees"] == sum(j["omega"] for j in jobs)
+
+
 def test_batch_equals_plain_path():
     from paper_2311_10290_amd import Batch, Graph
     jobs = _jobs()[:3]
